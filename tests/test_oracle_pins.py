@@ -1,0 +1,370 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test targets a part of the oracle where a plausible mistake (a dropped
+term, a wrong sign, a transposed operand, a wrong index) would show:
+
+* quadrature / basis identities (1-D rules, partition of unity);
+* pointwise flux identities (Euler homogeneity and eigenvalues, linearity of
+  the viscous flux in the gradient, Sutherland value, printed freestream state);
+* free-stream preservation on a perturbed trilinear mesh (signs and geometry of
+  eqs. hdg-grad, hdg-cons, hdg-trace);
+* the element conservation identity (partition of unity in eq. hdg-cons vs the
+  trace residual of eq. hdg-trace);
+* the inviscid trace identity (eq. num-flux-hdg with the average trace);
+* the Jacobian against central differences of the residual (eq. newton-linearization);
+* condensation against an independent LAPACK solve, and a brute-force solve
+  of the full uncondensed Newton system against condensation + recovery
+  (eqs. newton-local-block, local-elimination, schur-trace);
+* the additive-Schwarz operator and GMRES against dense linear algebra.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2608_27863_amd import synth
+from oracle import oracle as O
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def _wl(n=2, p=2, perturb=0.0, field=None, mach=0.8, noise=1e-3, nu_amp=0.0, seed=5, **kw):
+    mesh = synth.box_mesh((n, n, n), p=p, perturb=perturb, seed=seed)
+    field = field or (lambda x: synth.tgv_state(x, mach))
+    return synth.make_state(mesh, field, mach=mach, noise=noise, nu_amp=nu_amp, seed=seed, **kw)
+
+
+# ------------------------------------------------------------ quadrature
+@pytest.mark.parametrize("nq", [3, 4, 5, 6])
+def test_gauss_exactness(nq):
+    x, w = O.gauss(nq)
+    for k in range(2 * nq):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.dot(w, x ** k) - exact) < 1e-14
+    # degree 2nq is not integrated exactly (the rule really has nq points)
+    assert abs(np.dot(w, x ** (2 * nq)) - 2.0 / (2 * nq + 1)) > 1e-8
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_gll_nodes_match_library_roots(p):
+    assert np.allclose(O.gll(p), synth.gll_points(p), atol=1e-15, rtol=0)
+
+
+# --------------------------------------------------------- point physics
+def _prm(mach=1.25, re=1600.0, law=1, gamma=1.4):
+    return np.array([gamma, 0.71, re, mach, 5.0, 0.01, synth.dirk_alpha(), law])
+
+
+def _rand_state(rng, mach=1.25):
+    rho = rng.uniform(0.8, 1.3)
+    v = rng.uniform(-0.5, 0.5, 3)
+    p = 1.0 / (1.4 * mach ** 2) * rng.uniform(0.8, 1.2)
+    return np.array(synth._conserved(rho, v[0], v[1], v[2], p))
+
+
+def test_euler_flux_homogeneity_and_eigenvalues():
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        w = _rand_state(rng)
+        q = rng.standard_normal(15)
+        Fc, Fv, dFc, dFv = O.point_flux(w, q, 0.0, _prm())
+        J = dFc[:, :, :5]  # dFc_{c,j} / du_c'
+        for j in range(3):
+            assert np.allclose(J[:, j, :] @ w, Fc[:, j], rtol=1e-13, atol=1e-13)
+        assert np.all(dFc[:, :, 5:] == 0.0)
+        nvec = rng.standard_normal(3)
+        nvec /= np.linalg.norm(nvec)
+        An = np.einsum("cjk,j->ck", J, nvec)
+        rho, v = w[0], w[1:4] / w[0]
+        p = 0.4 * (w[4] - 0.5 * rho * v @ v)
+        c = math.sqrt(1.4 * p / rho)
+        vn = v @ nvec
+        ev = np.sort(np.linalg.eigvals(An).real)
+        assert np.allclose(ev, np.sort([vn - c, vn, vn, vn, vn + c]), atol=1e-12)
+
+
+def test_viscous_flux_linear_in_gradient():
+    rng = np.random.default_rng(1)
+    for nu in (0.0, 3e-4):
+        w = _rand_state(rng)
+        q = rng.standard_normal(15)
+        Fc, Fv, dFc, dFv = O.point_flux(w, q, nu, _prm())
+        assert np.allclose(dFv[:, :, 5:] @ q, Fv, rtol=1e-12, atol=1e-15)
+        _, Fv0, _, _ = O.point_flux(w, np.zeros(15), nu, _prm())
+        assert np.all(Fv0 == 0.0)
+        # the AV part is nu * q on every component (eq. av-total)
+        _, Fv_nonu, _, _ = O.point_flux(w, q, 0.0, _prm())
+        assert np.allclose(Fv - Fv_nonu, nu * q.reshape(5, 3), rtol=1e-12, atol=1e-18)
+
+
+def test_sutherland_value_from_shear_stress():
+    g = GOLD["sutherland_nondimensional"]
+    # rho = 1, v = 0, T = 1 (e = 1/(gamma (gamma-1) M^2)), pure shear d v1 / dy = 1
+    mach, re = 1.25, 1600.0
+    e = 1.0 / (1.4 * 0.4 * mach ** 2)
+    w = np.array([1.0, 0.0, 0.0, 0.0, e])
+    q = np.zeros(15)
+    q[3 * 1 + 1] = 1.0  # d(rho v1)/dy
+    _, Fv, _, _ = O.point_flux(w, q, 0.0, _prm(mach, re))
+    mu1 = g["c1"] / (1.0 + g["c2"])
+    assert abs(Fv[1, 1] - mu1 / re) < 1e-15  # tau_12 = mu (dv1/dy)
+    assert abs(Fv[2, 0] - mu1 / re) < 1e-15  # tau_21
+    # heat flux gamma mu / (Re Pr) de/dx with a temperature gradient only
+    q = np.zeros(15)
+    q[12] = 1.0  # d(rho E)/dx with rho, v constant: de/dx = 1
+    _, Fv, _, _ = O.point_flux(w, q, 0.0, _prm(mach, re))
+    assert abs(Fv[4, 0] - 1.4 * mu1 / (re * 0.71)) < 1e-15
+
+
+def test_printed_hypersonic_freestream_pressure():
+    g = GOLD["hypersonic_freestream"]
+    w = np.array([g["rho"], g["rho"] * 1.0, 0.0, 0.0, g["rho"] * g["E"]])
+    Fc, _, _, _ = O.point_flux(w, np.zeros(15), 0.0, _prm(mach=g["mach"], gamma=g["gamma"]))
+    p = Fc[1, 0] - 1.0  # rho v1 v1 + p
+    assert abs(p - g["p"]) <= g["p_half_ulp"]
+    assert abs(Fc[2, 1] - g["p"]) <= g["p_half_ulp"]  # delta_ij p: y-momentum, y-direction
+    assert abs(Fc[3, 2] - g["p"]) <= g["p_half_ulp"]
+
+
+def test_generator_tgv_kinetic_energy():
+    g = GOLD["tgv_kinetic_energy_t0"]
+    n = 48
+    h = 2 * math.pi / n
+    c = (np.arange(n) + 0.5) * h
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    for mach in (0.1, 1.25):
+        u = synth.tgv_state(np.stack([X, Y, Z], -1), mach)
+        ek = 0.5 * np.mean((u[..., 1] ** 2 + u[..., 2] ** 2 + u[..., 3] ** 2) / u[..., 0])
+        assert abs(ek - g["value"]) < 0.5 * 10 ** (-g["printed_digits"])
+        assert abs(ek - 0.125) < 1e-12  # the closed form: <rho |v|^2>/2 = 1/8 exactly
+        # T = 1: rho = gamma M^2 p
+        p = 0.4 * (u[..., 4] - 0.5 * (u[..., 1] ** 2 + u[..., 2] ** 2) / u[..., 0])
+        assert np.allclose(u[..., 0], 1.4 * mach ** 2 * p, rtol=1e-12)
+
+
+# ------------------------------------------------------------ geometry
+def test_volume_and_mass_partition():
+    wl = _wl(n=2, p=2, perturb=0.15)
+    m = wl.mesh
+    vols = [O.lib().hdgref_element_volume(2, O._p(O._f64(m.vert_xyz[m.elem_vert[e]].ravel())))
+            for e in range(m.n_elem)]
+    assert abs(sum(vols) - (2 * math.pi) ** 3) < 1e-10
+    E = O.element_system(wl, 3)
+    Np = 27
+    M = E[:Np, :Np]  # q_{0,0} block of A_qq is the mass matrix
+    assert abs(M.sum() - vols[3]) < 1e-12 * vols[3]
+    assert np.allclose(M, M.T, atol=1e-15)
+    for blk in range(1, 15):
+        assert np.array_equal(E[blk * Np:(blk + 1) * Np, blk * Np:(blk + 1) * Np], M)
+
+
+# ---------------------------------------------------- residual identities
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_free_stream_preservation(p):
+    const = np.array(synth._conserved(1.1, 0.3, -0.2, 0.1, 0.9))
+    field = lambda x: np.broadcast_to(const, x.shape[:-1] + (5,)) + 0.0 * x[..., :1]
+    wl = _wl(n=2, p=p, perturb=0.15, field=field, noise=0.0, nu_amp=5e-4)
+    wl.Q[:] = 0.0
+    sz = O.Sizes(wl.mesh)
+    Rh = np.zeros(wl.Uhat.shape)
+    for e in range(wl.mesh.n_elem):
+        E = O.element_system(wl, e, sz)
+        n = sz.n(e)
+        assert np.abs(E[:n, -1]).max() < 1e-13
+        t = np.concatenate([[0], np.cumsum(sz.face_sizes(e))])
+        for a, F in enumerate(wl.mesh.elem_face[e]):
+            Rh[sz.foff[F]:sz.foff[F + 1]] += E[n + t[a]:n + t[a + 1], -1]
+        assert np.abs(E[n:, -1]).max() > 1e-3  # element side alone is not zero
+    assert np.abs(Rh).max() < 1e-13
+
+
+@pytest.mark.parametrize("cfg_p", [2, 3])
+def test_element_conservation_identity(cfg_p):
+    wl = _wl(n=2, p=cfg_p, perturb=0.1, nu_amp=5e-4)
+    sz = O.Sizes(wl.mesh)
+    Np = (cfg_p + 1) ** 3
+    for e in (0, 5):
+        E = O.element_system(wl, e, sz)
+        n = sz.n(e)
+        M = E[:Np, :Np]
+        o = sz.noff[e]
+        dU = (wl.U - wl.Un)[5 * o:5 * (o + Np)].reshape(5, Np)
+        fs = sz.face_sizes(e)
+        t = np.concatenate([[0], np.cumsum(fs)])
+        for c in range(5):
+            Ru_sum = E[(15 + c) * Np:(16 + c) * Np, -1].sum()
+            trace_sum = 0.0
+            for a in range(6):
+                nfp = fs[a] // 5
+                trace_sum += E[n + t[a] + c * nfp:n + t[a] + (c + 1) * nfp, -1].sum()
+            expect = wl.alpha * (M @ dU[c]).sum() + wl.dt * trace_sum
+            assert abs(Ru_sum - expect) < 1e-12 * max(1.0, abs(expect))
+        # gradient equations: sum_i R_q = int q - int_dK uhat n (int u d_j(1) = 0)
+        B = E[:n, n:n + t[-1]]
+        Uh_e = O.gather_trace(wl, sz, e, wl.Uhat)
+        Q = wl.Q[15 * o:15 * (o + Np)].reshape(15, Np)
+        for r in range(15):
+            lhs = E[r * Np:(r + 1) * Np, -1].sum()
+            rhs = (M @ Q[r]).sum() + (B[r * Np:(r + 1) * Np] @ Uh_e).sum()
+            assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(rhs))
+
+
+def test_inviscid_trace_identity():
+    wl = _wl(n=2, p=2, perturb=0.1, reynolds=1e300, nu_amp=0.0)
+    m = wl.mesh
+    sz = O.Sizes(m)
+    Np, nf = 27, 3
+    # Uhat = average of the two sides' traces of u_h at the face nodes
+    Uh = np.zeros_like(wl.Uhat)
+    for F in range(m.n_face):
+        acc = np.zeros((5, nf * nf))
+        for s in range(2):
+            e, lf = m.face_elem[F, s]
+            d, side = lf // 2, lf % 2
+            t = [a for a in range(3) if a != d]
+            o = sz.noff[e]
+            U = wl.U[5 * o:5 * (o + Np)].reshape(5, nf, nf, nf)  # [c][i2][i1][i0]
+            idx = [slice(None)] * 3
+            idx[2 - d] = nf - 1 if side else 0
+            tr = U[(slice(None),) + tuple(idx)]  # axes: remaining (t1 slower, t0 faster)
+            acc += tr.reshape(5, -1)
+        Uh[sz.foff[F]:sz.foff[F + 1]] = (acc / 2).ravel()
+    Rh = np.zeros(wl.Uhat.shape)
+    for e in range(m.n_elem):
+        E = O.element_system(wl, e, sz, Uhat=Uh)
+        n = sz.n(e)
+        t = np.concatenate([[0], np.cumsum(sz.face_sizes(e))])
+        for a, F in enumerate(m.elem_face[e]):
+            Rh[sz.foff[F]:sz.foff[F + 1]] += E[n + t[a]:n + t[a + 1], -1]
+    assert np.abs(Rh).max() < 1e-13 * max(1.0, np.abs(wl.U).max())
+
+
+@pytest.mark.parametrize("p,nu_amp,law", [(2, 5e-4, 1), (3, 0.0, 0), (1, 5e-4, 1)])
+def test_jacobian_matches_finite_differences(p, nu_amp, law):
+    wl = _wl(n=2, p=p, perturb=0.1, nu_amp=nu_amp, visc_law=law, reynolds=50.0)
+    sz = O.Sizes(wl.mesh)
+    e = 6
+    E = O.element_system(wl, e, sz)
+    n, f = sz.n(e), sz.f(e)
+    Np = n // 20
+    o = sz.noff[e]
+    rng = np.random.default_rng(3)
+    J = E[:, :n + f]
+    for trial in range(3):
+        dQ = rng.standard_normal(15 * Np)
+        dU = rng.standard_normal(5 * Np) * np.repeat([1.0, 0.3, 0.3, 0.3, 1.0], Np) * 1e-1
+        dUh_e = rng.standard_normal(f) * 1e-1
+        # global perturbation of this element's faces only
+        dUh = np.zeros_like(wl.Uhat)
+        t = np.concatenate([[0], np.cumsum(sz.face_sizes(e))])
+        for a, F in enumerate(wl.mesh.elem_face[e]):
+            dUh[sz.foff[F]:sz.foff[F + 1]] = dUh_e[t[a]:t[a + 1]]
+        dir_e = np.concatenate([dQ, dU, dUh_e])
+        h = 1e-6
+        res = []
+        for s in (+1, -1):
+            Q = wl.Q.copy()
+            U = wl.U.copy()
+            Q[15 * o:15 * (o + Np)] += s * h * dQ
+            U[5 * o:5 * (o + Np)] += s * h * dU
+            res.append(O.element_system(wl, e, sz, U=U, Q=Q, Uhat=wl.Uhat + s * h * dUh)[:, -1])
+        fd = (res[0] - res[1]) / (2 * h)
+        an = J @ dir_e
+        for rows in (slice(0, 15 * Np), slice(15 * Np, n), slice(n, n + f)):
+            scale = np.abs(an[rows]).max()
+            assert np.abs(fd[rows] - an[rows]).max() < 1e-7 * scale + 1e-12
+
+
+# ------------------------------------------------------------ algebra
+def test_condensation_matches_lapack():
+    wl = synth.config(0)
+    sz = O.Sizes(wl.mesh)
+    for e in (0, 17):
+        E = O.element_system(wl, e, sz)
+        n = sz.n(e)
+        SK, gK, X = O.condense(E, n)
+        A, B, C, D, Rq, Ru = O.split(E, n)
+        Xl = np.linalg.solve(A, np.concatenate([B, Rq[:, None]], axis=1))
+        assert np.linalg.norm(Xl - X) / np.linalg.norm(Xl) < 1e-12
+        assert np.linalg.norm(D - C @ Xl[:, :-1] - SK) / np.linalg.norm(SK) < 1e-13
+        assert np.linalg.norm(-Ru + C @ Xl[:, -1] - gK) / np.linalg.norm(gK) < 1e-13
+        # recovery satisfies the first block row of eq. newton-local-block
+        dUh = np.random.default_rng(e).standard_normal(SK.shape[0])
+        dW = -(X[:, -1] + X[:, :-1] @ dUh)
+        assert np.linalg.norm(A @ dW + B @ dUh + Rq) < 1e-11 * np.linalg.norm(Rq)
+
+
+def _condensed(wl):
+    sz = O.Sizes(wl.mesh)
+    Es = [O.element_system(wl, e, sz) for e in range(wl.mesh.n_elem)]
+    outs = [O.condense(E, sz.n(e)) for e, E in enumerate(Es)]
+    ts = O.TraceSystem(wl, [o[0] for o in outs], [o[1] for o in outs])
+    return sz, Es, outs, ts
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_brute_force_uncondensed_solve(p):
+    """Solving the full Newton system (all interior and trace unknowns) equals
+    condensation, a trace solve and recovery."""
+    wl = _wl(n=2, p=p, perturb=0.1, nu_amp=5e-4, mach=1.25)
+    m = wl.mesh
+    sz, Es, outs, ts = _condensed(wl)
+    ni = [sz.n(e) for e in range(m.n_elem)]
+    ioff = np.concatenate([[0], np.cumsum(ni)])
+    Ni, Nt = ioff[-1], ts.N
+    K = np.zeros((Ni + Nt, Ni + Nt))
+    rhs = np.zeros(Ni + Nt)
+    for e, E in enumerate(Es):
+        n = ni[e]
+        A, B, C, D, Rq, Ru = O.split(E, n)
+        tidx = Ni + ts.patch_index(e)
+        ii = np.arange(ioff[e], ioff[e + 1])
+        K[np.ix_(ii, ii)] += A
+        K[np.ix_(ii, tidx)] += B
+        K[np.ix_(tidx, ii)] += C
+        K[np.ix_(tidx, tidx)] += D
+        rhs[ii] -= Rq
+        np.add.at(rhs, tidx, -Ru)
+    sol = np.linalg.solve(K, rhs)
+    dUh = O.dense_solve(ts.dense(), ts.g)
+    assert np.linalg.norm(sol[Ni:] - dUh) < 1e-10 * np.linalg.norm(dUh)
+    for e in range(m.n_elem):
+        dW = O.recover(wl, sz, e, outs[e][2], dUh)
+        ref = sol[ioff[e]:ioff[e + 1]]
+        assert np.linalg.norm(dW - ref) < 1e-10 * np.linalg.norm(ref)
+
+
+def test_matvec_asm_and_gmres_against_dense():
+    wl = _wl(n=2, p=2, perturb=0.1, nu_amp=5e-4, mach=1.25)
+    sz, Es, outs, ts = _condensed(wl)
+    S = ts.dense()
+    x = wl.x
+    assert np.allclose(ts.matvec(x), S @ x, rtol=0, atol=1e-13 * np.abs(S).max())
+    # dense additive Schwarz: sum_r R_r^T inv(S_r) R_r
+    Minv = np.zeros_like(S)
+    for r in range(wl.mesh.n_elem):
+        idx = ts.patch_index(r)
+        Sr = S[np.ix_(idx, idx)]
+        assert np.array_equal(Sr, ts.patch_matrix(r))
+        Rr = np.zeros((idx.size, S.shape[0]))
+        Rr[np.arange(idx.size), idx] = 1.0
+        Minv += Rr.T @ np.linalg.inv(Sr) @ Rr
+    assert np.allclose(ts.asm_apply(x), Minv @ x, rtol=0, atol=1e-12 * np.abs(Minv @ x).max())
+    # GMRES converged to a tight tolerance equals the dense solution
+    xg, hist = O.gmres(ts, ts.g, 200, tol=1e-13)
+    xd = np.linalg.solve(S, ts.g)
+    assert np.linalg.norm(xg - xd) < 1e-10 * np.linalg.norm(xd)
+    assert np.all(np.diff(hist) <= 1e-14 * hist[0])
+    # fixed m: the iterate minimises the preconditioned residual over K_m
+    m = 5
+    xm, hm = O.gmres(ts, ts.g, m)
+    r = Minv @ (ts.g - S @ xm)
+    assert abs(np.linalg.norm(r) - hm[-1]) < 1e-10 * hm[0]
+    Kb = [Minv @ ts.g]
+    for _ in range(m - 1):
+        Kb.append(Minv @ (S @ Kb[-1]))
+    Kb = np.array(Kb).T
+    c, *_ = np.linalg.lstsq(Minv @ S @ Kb, Minv @ ts.g, rcond=None)
+    assert np.linalg.norm(Kb @ c - xm) < 1e-8 * np.linalg.norm(xm)
