@@ -1,0 +1,249 @@
+/*
+ * hdg.h -- C ABI of libhdg: the element-local hot path of an HDG
+ * Newton-GMRES solver for the compressible Navier-Stokes equations on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Welter, Collin, Nguyen, Peraire, "A Massively Parallel Hybridizable
+ * Discontinuous Galerkin Solver for Direct Numerical Simulation of
+ * Compressible Flows on GPUs".  Section references below are to that paper.
+ *
+ * One Newton iteration of a DIRK stage (sections 2.4-3.3) is
+ *   hdg_local_residual_jacobian   element residuals and Jacobian blocks
+ *   hdg_condense                  static condensation per element
+ *   hdg_assemble_trace            assembly of the condensed trace system
+ *   hdg_asm_setup                 additive-Schwarz local inverses
+ *   hdg_gmres                     left-preconditioned GMRES on S dUhat = g
+ *      (uses hdg_face_matvec and hdg_asm_block_apply)
+ *   hdg_recover_interior          interior correction from the trace one
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named "host" are host memory; every other array pointer is
+ *   device memory owned by the caller (the library never frees it).  The
+ *   context owns only its own tables (freed by hdg_destroy).
+ * - `stream` is a hipStream_t passed as void*; every call only enqueues work
+ *   on it (no host synchronisation, no allocation), so calls can be captured
+ *   in a HIP graph.  NULL is the default stream.
+ * - Return value: HDG_OK, or a negative hdg_status.  Arguments are checked
+ *   on the host before anything is enqueued; a failed launch returns
+ *   HDG_ERR_DEVICE.  Numerical failures never synchronise: they are written
+ *   to device `info` arrays.
+ * - Unknowns (nondimensional, rho_0 = |v_0| = L = T_0 = 1):
+ *     U  : conserved variables u = (rho, rho v1, rho v2, rho v3, rho E)
+ *     Q  : gradient q = grad u, q_{c,j} = d u_c / d x_j   (eq. mixed-variable)
+ *     Uh : single-valued face trace of u                   (eq. spaces)
+ * - Element e has degree p_e (1..4), N_p = (p_e+1)^3 Gauss-Lobatto nodes in
+ *   tensor order (x fastest).  Face F has degree p_F = max of its sides and
+ *   N_fp = (p_F+1)^2 trace nodes.  Volume quadrature: (p_e+2)^3 Gauss
+ *   points; face quadrature: (p_F+2)^2 Gauss points.
+ * - Packed node arrays (layout [e][field][node], elements back to back;
+ *   element e starts at field_count * node_off[e]):
+ *     Q [15 N_p] fields 3c+j;  U, Un [5 N_p];  nu [N_p];  dQU [20 N_p]
+ *     (dQU fields 0..14 are dq_{c,j}, 15..19 are du_c).
+ * - Packed face arrays ([F][c][node], face F starts at face_off[F]):
+ *     Uhat, Ub, g, dUhat, x, y, r, z.  Total length N_uh = face_off[n_face].
+ * - Element-local trace order: local faces -x,+x,-y,+y,-z,+z, each
+ *   [c][node]; f_e = sum over the 6 faces of 5 N_fp; n_e = 20 N_p.
+ * - Element system E^K (one per element, ROW-major, n+f rows of stride
+ *   ldE = n+f+1 rounded up to a multiple of 8; columns n+f+1 .. ldE-1 are
+ *   padding, written as 0), the linearised local problem of
+ *   eq. newton-local-block bordered by the element's trace equations:
+ *         [ A  B  R_qu ]   rows 0..n-1     A = d(R_q,R_u)/d(Q,U)   (n x n)
+ *         [ C  D  R_uh ]   rows n..n+f-1   B = d(R_q,R_u)/d(Uh^K)  (n x f)
+ *                                          C = d(R_uh^K)/d(Q,U)    (f x n)
+ *                                          D = d(R_uh^K)/d(Uh^K)   (f x f)
+ *   Element e's system starts at E_off[e] doubles (relative to E_off[e0]
+ *   for a chunk starting at element e0).
+ * - Condensed element output SK (per element, column-major f x (f+1)):
+ *   [ S^K | g^K ] with S^K = D - C A^{-1} B and g^K = -R_uh + C A^{-1} R_qu
+ *   (eqs. local-elimination, schur-trace).  Element e at SK_off[e].
+ * - Assembled trace operator S: block-sparse rows, one block row per face,
+ *   block (F, F') of size (5 N_fp(F)) x (5 N_fp(F')) stored column-major at
+ *   bsr_val_off[k] for k in bsr_row_ptr[F] .. bsr_row_ptr[F+1]-1, column
+ *   face bsr_col[k] (ascending).  Pattern built by hdg_create.
+ * - Layout arrays are obtained with hdg_layout().
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdg_ctx hdg_ctx;
+
+typedef enum {
+    HDG_OK = 0,
+    HDG_ERR_INVALID_ARGUMENT = -1,
+    HDG_ERR_UNSUPPORTED = -2,
+    HDG_ERR_OUT_OF_MEMORY = -3,
+    HDG_ERR_DEVICE = -4,
+    HDG_ERR_WORKSPACE = -5
+} hdg_status;
+
+/* Arithmetic of the element condensation and of the Schwarz blocks. */
+typedef enum {
+    HDG_FP64 = 0,   /* FP64 throughout                                          */
+    HDG_MIXED = 1   /* FP32 LU / triangular solves with FP32 accumulation,
+                       FP64-residual iterative refinement of A^{-1}[B|R_qu],
+                       FP64 Schur product; Schwarz inverses stored in FP32     */
+} hdg_precision;
+
+/* Mesh: conforming hexahedra, all elements identically oriented (every face is
+ * seen with the same tangential axes from both sides).  Host memory, copied. */
+typedef struct hdg_mesh_desc {
+    int n_elem, n_face, n_vert;
+    const double *vert_xyz;      /* host [n_vert][3]                                   */
+    const int *elem_vert;        /* host [n_elem][8], tensor order (x fastest)        */
+    const int *elem_face;        /* host [n_elem][6], faces -x,+x,-y,+y,-z,+z          */
+    const int *face_elem;        /* host [n_face][2][2]: (elem, local face) of side 0
+                                    and side 1; side 1 = (-1,-1) on a boundary face.
+                                    The face normal points out of side 0.              */
+    const signed char *face_bc;  /* host [n_face]: 0 interior/periodic, 1 Dirichlet    */
+    const signed char *elem_p;   /* host [n_elem]: degree 1..4                         */
+} hdg_mesh_desc;
+
+/* Physical and time-discretisation constants (section 2, section 5). */
+typedef struct hdg_phys {
+    double gamma;     /* ratio of specific heats                                   */
+    double prandtl;   /* Pr, heat flux gamma mu / (Re Pr) de/dx (eq. thermal-conductivity) */
+    double reynolds;  /* viscosity mu(T) / Re                                      */
+    double mach;      /* T = gamma (gamma-1) M^2 e                                 */
+    double tau;       /* HDG stabilisation tau_h = tau * I (eq. num-flux-hdg)       */
+    double dt;        /* time step multiplying N in eq. fully-discrete-local        */
+    double alpha;     /* DIRK diagonal d_ii multiplying M (U - U^n)                */
+    int visc_law;     /* 0: mu = 1; 1: mu = 1.4042 T^1.5 / (T + 0.40417) (eq. tgv-sutherland) */
+} hdg_phys;
+
+/* Create a context on the current HIP device: copies the mesh, computes the
+ * quadrature tables and geometry (inverse Jacobians, weights, area-weighted
+ * normals), the assembly maps and the block-sparse pattern.  Blocking; the
+ * only call that allocates device memory.  Returns HDG_ERR_INVALID_ARGUMENT
+ * for an inconsistent mesh (bad indices, degree outside 1..4, a face whose two
+ * sides are not opposite local faces, or a non-positive Jacobian). */
+int hdg_create(const hdg_mesh_desc *mesh, const hdg_phys *phys, hdg_ctx **out);
+void hdg_destroy(hdg_ctx *ctx);
+const char *hdg_status_string(int status);
+
+/* Layout queries: hdg_layout copies a host array of int64 into dst (host). */
+typedef enum {
+    HDG_LAYOUT_NODE_OFF = 0,    /* [n_elem+1] node offsets                            */
+    HDG_LAYOUT_FACE_OFF = 1,    /* [n_face+1] face trace offsets (doubles)            */
+    HDG_LAYOUT_E_OFF = 2,       /* [n_elem+1] element-system offsets (doubles)        */
+    HDG_LAYOUT_SK_OFF = 3,      /* [n_elem+1] condensed-output offsets (doubles)      */
+    HDG_LAYOUT_BSR_ROW_PTR = 4, /* [n_face+1]                                         */
+    HDG_LAYOUT_BSR_COL = 5,     /* [nnzb]                                             */
+    HDG_LAYOUT_BSR_VAL_OFF = 6, /* [nnzb+1] block offsets (doubles)                   */
+    HDG_LAYOUT_ASM_OFF = 7,     /* [n_elem+1] Schwarz block offsets (entries)          */
+    HDG_LAYOUT_ELEM_N = 8,      /* [n_elem] n_e                                       */
+    HDG_LAYOUT_ELEM_F = 9       /* [n_elem] f_e                                       */
+} hdg_layout_kind;
+int hdg_layout(const hdg_ctx *ctx, int kind, int64_t *dst, int64_t capacity);
+/* Length of a layout array (so the caller can size dst). */
+int64_t hdg_layout_length(const hdg_ctx *ctx, int kind);
+
+/* Workspace sizes in bytes (caller allocates, 256-byte aligned).  `op` is the
+ * entry point: 1 hdg_condense (for a chunk of ne elements starting at e0),
+ * 2 hdg_asm_setup, 3 hdg_asm_block_apply, 4 hdg_gmres (with Krylov dimension
+ * m = ne). */
+int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, size_t *bytes);
+
+/*
+ * Element residuals and Jacobians (steps of eqs. hdg-grad, hdg-cons with the
+ * DIRK mass term of eq. fully-discrete-local, hdg-trace; the flux of
+ * eq. num-flux-hdg with tau_h = tau I; fluxes of eqs. convective-flux,
+ * viscous-flux, stress-heat, av-total; Jacobians of eq. newton-linearization).
+ * For elements e0 .. e0+ne-1 writes E^K completely (every entry), where
+ *   R_q[(c,j),i] = int_K q_cj phi_i + int_K u_c d_j phi_i - int_dK uh_c phi_i n_j
+ *   R_u[c,i]     = alpha int_K (u-u^n)_c phi_i - dt int_K (F^c - F^v)_cj d_j phi_i
+ *                  + dt int_dK fh_c phi_i
+ *   R_uh^K[F,c,a]= int_F fh_c mu_a            (interior / periodic faces)
+ *                = int_F (uh - ub)_c mu_a     (Dirichlet faces, face_bc = 1)
+ *   fh = (F^c(uh) - F^v(uh, q)) . n + tau (u - uh),  F^v includes nu q.
+ * nu is frozen (no derivative).  Ub is read only on Dirichlet faces (may be
+ * NULL when the mesh has none).  E points at element e0's system.  `work`
+ * (hdg_workspace_size op 0) holds the quadrature-point fluxes and Jacobians
+ * (the point kernel's output, read by the assembly kernel).
+ */
+int hdg_local_residual_jacobian(hdg_ctx *ctx, int e0, int ne,
+                                const double *Q, const double *U, const double *Un,
+                                const double *Uhat, const double *nu, const double *Ub,
+                                double *E, void *work, size_t work_bytes, void *stream);
+
+/*
+ * Static condensation (eqs. local-elimination, schur-trace) of elements
+ * e0 .. e0+ne-1.  E (element e0's system first) is overwritten:
+ *  HDG_FP64: partial LU with partial pivoting of the first n columns of E
+ *    (pivots chosen among rows 0..n-1), the elimination carried through the
+ *    trace rows and the [B | R_qu] columns.  Afterwards rows 0..n-1 hold U (upper
+ *    triangle of the n x n block) and L^{-1} P [B | R_qu]; rows n.. hold
+ *    [S^K | -g^K].
+ *  HDG_MIXED: A is factorised in FP32 in the workspace, X = A^{-1}[B | R_qu] is
+ *    refined `refine_steps` (>= 1) times with FP64 residuals [B|R_qu] - A X, S^K
+ *    and g^K are formed with FP64 products; X is then stored in place of
+ *    [B | R_qu] (rows 0..n-1, columns n..n+f).
+ * SK (all elements, element e at SK_off[e]) receives [S^K | g^K].
+ * info[e] (device, all elements) = 0, or k+1 if the k-th pivot was zero or
+ * not finite (the element's outputs are then undefined).
+ */
+int hdg_condense(hdg_ctx *ctx, int prec, int refine_steps, int e0, int ne, double *E,
+                 double *SK, int *info, void *work, size_t work_bytes, void *stream);
+
+/*
+ * Assembly of S = sum_K P_K^T S^K P_K and g = sum_K P_K^T g^K (eq. schur-trace)
+ * into the block-sparse S (all blocks written) and g.  Each block and face is
+ * a gather over its element contributions in a fixed order (bit-reproducible,
+ * no atomics).  Needs SK of every element.
+ */
+int hdg_assemble_trace(hdg_ctx *ctx, const double *SK, double *S_bsr, double *g, void *stream);
+
+/* y = S x over the block-sparse operator (a trace-space matvec inside GMRES). */
+int hdg_face_matvec(hdg_ctx *ctx, const double *S_bsr, const double *x, double *y, void *stream);
+
+/*
+ * One-level additive Schwarz set-up (eq. additive-schwarz): for every element
+ * r, S_r = R_r S R_r^T (its six faces' blocks of the assembled S) is inverted
+ * by LU with partial pivoting; the inverse is stored in Sinv at ASM_off[r]
+ * entries, column-major f_r x f_r, as double (HDG_FP64) or float (HDG_MIXED).
+ * info[r] = 0 or k+1 on a zero pivot.
+ */
+int hdg_asm_setup(hdg_ctx *ctx, int prec, const double *S_bsr, void *Sinv, int *info,
+                  void *work, size_t work_bytes, void *stream);
+
+/*
+ * z = sum_r R_r^T S_r^{-1} R_r r (eq. additive-schwarz): restriction to each
+ * element's faces, the local solve with the stored inverse (FP64 data, or FP32
+ * data with FP64 accumulation), and prolongation summed over the elements
+ * sharing a face in a fixed order.
+ */
+int hdg_asm_block_apply(hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
+                        void *work, size_t work_bytes, void *stream);
+
+/*
+ * One cycle of left-preconditioned GMRES(m) on S dUhat = g, x0 = 0
+ * (section 3.2): Arnoldi with classical Gram-Schmidt applied twice, Givens
+ * rotations and the triangular solve on the device, all FP64.  res_hist
+ * (device, m+1 doubles) receives ||M^{-1}(g - S x_j)||_2, j = 0..m.
+ * m in 1..200.
+ */
+int hdg_gmres(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, const double *g,
+              int m, double *dUhat, double *res_hist, void *work, size_t work_bytes,
+              void *stream);
+
+/*
+ * Interior recovery (eq. local-elimination): for elements e0 .. e0+ne-1,
+ * d(Q,U)^K = -A^{-1} (R_qu + B dUh^K), from E as left by hdg_condense with the
+ * same `prec` (HDG_FP64: back substitution with U; HDG_MIXED: -(x_r + X_B dUh)).
+ * dQU is the packed node array (all elements).
+ */
+int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E,
+                         const double *dUhat, double *dQU, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDG_H */

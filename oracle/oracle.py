@@ -217,8 +217,19 @@ class TraceSystem:
                         self.blocks[key] = self.blocks[key] + blk
                     else:
                         self.blocks[key] = blk.copy()
-        # Dirichlet faces: the trace equation is the element side's only
         self.asm_inv = None
+
+    @classmethod
+    def from_blocks(cls, wl, blocks, g):
+        """A trace system with given blocks {(F, G): array} and right-hand side g."""
+        ts = cls.__new__(cls)
+        ts.wl = wl
+        ts.sizes = Sizes(wl.mesh)
+        ts.N = int(ts.sizes.foff[-1])
+        ts.blocks = {k: np.array(v, dtype=np.float64) for k, v in blocks.items()}
+        ts.g = np.array(g, dtype=np.float64)
+        ts.asm_inv = None
+        return ts
 
     def matvec(self, x):
         y = np.zeros(self.N)

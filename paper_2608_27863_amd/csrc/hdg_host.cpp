@@ -1,0 +1,583 @@
+// Host side of libhdg: context creation (quadrature tables, geometry,
+// assembly maps, block-sparse pattern), layout queries, argument checks and
+// the C-ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "hdg_internal.h"
+
+using hdg::DevMesh;
+
+namespace {
+
+// ---------------------------------------------------------------- 1-D rules
+// Legendre P_n and P_n' by the three-term recurrence.
+void legendre(int n, double x, double &P, double &dP) {
+    double pm1 = 1.0, p = x;
+    if (n == 0) { P = 1.0; dP = 0.0; return; }
+    for (int k = 1; k < n; ++k) {
+        double pn = ((2 * k + 1) * x * p - k * pm1) / (k + 1);
+        pm1 = p;
+        p = pn;
+    }
+    P = p;
+    dP = n * (x * p - pm1) / (x * x - 1.0);
+}
+
+void gauss_rule(int nq, double *x, double *w) {
+    for (int i = 0; i < nq; ++i) {
+        // initial guess from the asymptotic node location, ascending order
+        double t = std::cos(M_PI * (nq - i - 0.25) / (nq + 0.5));
+        for (int it = 0; it < 200; ++it) {
+            double P, dP;
+            legendre(nq, t, P, dP);
+            double step = P / dP;
+            t -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        double P, dP;
+        legendre(nq, t, P, dP);
+        x[i] = t;
+        w[i] = 2.0 / ((1.0 - t * t) * dP * dP);
+    }
+}
+
+// Gauss-Lobatto nodes: endpoints and the zeros of P_p', which are the Gauss
+// points of the Jacobi weight (1-x^2); Newton on P_p' using
+// P_p'' = (2x P_p' - p(p+1) P_p) / (1 - x^2).
+void lobatto_nodes(int p, double *r) {
+    r[0] = -1.0;
+    r[p] = 1.0;
+    for (int i = 1; i < p; ++i) {
+        double t = -std::cos(M_PI * i / p);
+        for (int it = 0; it < 200; ++it) {
+            double P, dP;
+            legendre(p, t, P, dP);
+            double d2P = (2.0 * t * dP - p * (p + 1.0) * P) / (1.0 - t * t);
+            double step = dP / d2P;
+            t -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        r[i] = t;
+    }
+}
+
+// Lagrange basis on nodes r[0..p] (barycentric form) and its derivative at t.
+void lagrange_eval(int p, const double *r, double t, double *val, double *der) {
+    double bw[8];
+    for (int a = 0; a <= p; ++a) {
+        double prod = 1.0;
+        for (int b = 0; b <= p; ++b)
+            if (b != a) prod *= (r[a] - r[b]);
+        bw[a] = 1.0 / prod;
+    }
+    for (int a = 0; a <= p; ++a) {
+        if (t == r[a]) {
+            for (int b = 0; b <= p; ++b) val[b] = (b == a) ? 1.0 : 0.0;
+            // derivative at a node: l_b'(r_a) = (bw_b / bw_a) / (r_a - r_b), l_a' = -sum_{b!=a}
+            if (der) {
+                double s = 0.0;
+                for (int b = 0; b <= p; ++b) {
+                    if (b == a) continue;
+                    der[b] = (bw[b] / bw[a]) / (r[a] - r[b]);
+                    s += der[b];
+                }
+                der[a] = -s;
+            }
+            return;
+        }
+    }
+    double ell = 1.0;
+    for (int b = 0; b <= p; ++b) ell *= (t - r[b]);
+    double S1 = 0.0;
+    for (int b = 0; b <= p; ++b) S1 += 1.0 / (t - r[b]);
+    for (int a = 0; a <= p; ++a) {
+        double v = ell * bw[a] / (t - r[a]);
+        val[a] = v;
+        // d/dt [ell(t) bw_a / (t - r_a)] = v * (S1 - 1/(t-r_a))
+        if (der) der[a] = v * (S1 - 1.0 / (t - r[a]));
+    }
+}
+
+void build_tables(double *T) {
+    std::memset(T, 0, sizeof(double) * hdg::kTblSize);
+    for (int nq = 3; nq <= 6; ++nq) {
+        double x[8], w[8];
+        gauss_rule(nq, x, w);
+        for (int g = 0; g < nq; ++g) T[hdg::tbl_W(nq, g)] = w[g];
+    }
+    for (int p = 1; p <= hdg::kMaxP; ++p) {
+        double r[8];
+        lobatto_nodes(p, r);
+        for (int q = 1; q <= hdg::kMaxP; ++q) {
+            double x[8], w[8];
+            gauss_rule(q + 2, x, w);
+            for (int s = 0; s < q + 2; ++s) {
+                double val[8], der[8];
+                lagrange_eval(p, r, x[s], val, der);
+                for (int a = 0; a <= p; ++a) {
+                    T[hdg::tbl_L(p, q, a, s)] = val[a];
+                    if (q == p) T[hdg::tbl_D(p, a, s)] = der[a];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- geometry
+// Trilinear map of the 8 vertices (tensor order): Jacobian J[i][d] = dx_i/dxi_d.
+void map_jacobian(const double *X8, const double xi[3], double J[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int d = 0; d < 3; ++d) J[i][d] = 0.0;
+    for (int v = 0; v < 8; ++v) {
+        double f[3], df[3];
+        for (int d = 0; d < 3; ++d) {
+            double s = ((v >> d) & 1) ? 0.5 : -0.5;
+            f[d] = 0.5 + s * xi[d];
+            df[d] = s;
+        }
+        double g[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+        for (int i = 0; i < 3; ++i)
+            for (int d = 0; d < 3; ++d) J[i][d] += g[d] * X8[3 * v + i];
+    }
+}
+
+// Cofactor inverse: G = J^{-1}, returns det J.
+double invert3(const double J[3][3], double G[3][3]) {
+    double C[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            C[i][j] = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
+        }
+    double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < 3; ++j) G[d][j] = C[j][d] / det;
+    return det;
+}
+
+template <class T>
+int upload(hdg_ctx *ctx, const std::vector<T> &h, const T **dst) {
+    size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return HDG_ERR_OUT_OF_MEMORY;
+    ctx->allocations.push_back(p);
+    if (!h.empty() && hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return HDG_ERR_DEVICE;
+    *dst = static_cast<const T *>(p);
+    return HDG_OK;
+}
+
+int trace_size(int pf) { return 5 * (pf + 1) * (pf + 1); }
+
+}  // namespace
+
+// ====================================================================== API
+extern "C" {
+
+const char *hdg_status_string(int s) {
+    switch (s) {
+        case HDG_OK: return "ok";
+        case HDG_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case HDG_ERR_UNSUPPORTED: return "unsupported";
+        case HDG_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case HDG_ERR_DEVICE: return "HIP device error";
+        case HDG_ERR_WORKSPACE: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+void hdg_destroy(hdg_ctx *ctx) {
+    if (!ctx) return;
+    for (void *p : ctx->allocations) (void)hipFree(p);
+    delete ctx;
+}
+
+int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
+    if (!m || !phys || !out) return HDG_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (m->n_elem <= 0 || m->n_face <= 0 || m->n_vert <= 0 || !m->vert_xyz || !m->elem_vert ||
+        !m->elem_face || !m->face_elem || !m->face_bc || !m->elem_p)
+        return HDG_ERR_INVALID_ARGUMENT;
+    if (!(phys->gamma > 1.0) || !(phys->prandtl > 0.0) || !(phys->reynolds > 0.0) || !(phys->mach > 0.0) ||
+        !(phys->dt > 0.0) || !(phys->tau >= 0.0) || !(phys->alpha >= 0.0) ||
+        (phys->visc_law != 0 && phys->visc_law != 1))
+        return HDG_ERR_INVALID_ARGUMENT;
+    const int ne = m->n_elem, nf = m->n_face;
+    hdg_ctx *ctx = new (std::nothrow) hdg_ctx();
+    if (!ctx) return HDG_ERR_OUT_OF_MEMORY;
+    auto fail = [&](int st) { hdg_destroy(ctx); return st; };
+    ctx->n_elem = ne;
+    ctx->n_face = nf;
+    ctx->phys = {phys->gamma, phys->prandtl, phys->reynolds, phys->mach, phys->tau, phys->dt, phys->alpha,
+                 phys->visc_law};
+    // ---- validate topology
+    ctx->elem_p.resize(ne);
+    for (int e = 0; e < ne; ++e) {
+        int p = m->elem_p[e];
+        if (p < 1 || p > hdg::kMaxP) return fail(HDG_ERR_INVALID_ARGUMENT);
+        ctx->elem_p[e] = p;
+        for (int v = 0; v < 8; ++v)
+            if (m->elem_vert[8 * e + v] < 0 || m->elem_vert[8 * e + v] >= m->n_vert) return fail(HDG_ERR_INVALID_ARGUMENT);
+    }
+    ctx->elem_face.assign(m->elem_face, m->elem_face + 6 * ne);
+    ctx->face_elem.assign(m->face_elem, m->face_elem + 4 * nf);
+    ctx->face_bc.resize(nf);
+    ctx->face_p.assign(nf, 0);
+    for (int F = 0; F < nf; ++F) {
+        ctx->face_bc[F] = m->face_bc[F];
+        if (m->face_bc[F] != 0 && m->face_bc[F] != 1) return fail(HDG_ERR_INVALID_ARGUMENT);
+        int e0 = ctx->face_elem[4 * F], l0 = ctx->face_elem[4 * F + 1];
+        int e1 = ctx->face_elem[4 * F + 2], l1 = ctx->face_elem[4 * F + 3];
+        if (e0 < 0 || e0 >= ne || l0 < 0 || l0 > 5) return fail(HDG_ERR_INVALID_ARGUMENT);
+        if (ctx->elem_face[6 * e0 + l0] != F) return fail(HDG_ERR_INVALID_ARGUMENT);
+        ctx->face_p[F] = ctx->elem_p[e0];
+        if (e1 >= 0) {
+            if (e1 >= ne || l1 < 0 || l1 > 5 || ctx->elem_face[6 * e1 + l1] != F) return fail(HDG_ERR_INVALID_ARGUMENT);
+            if (l0 / 2 != l1 / 2 || l0 == l1) return fail(HDG_ERR_INVALID_ARGUMENT);  // opposite sides
+            if (ctx->face_bc[F]) return fail(HDG_ERR_INVALID_ARGUMENT);
+            ctx->face_p[F] = std::max(ctx->face_p[F], ctx->elem_p[e1]);
+        } else if (!ctx->face_bc[F]) {
+            return fail(HDG_ERR_INVALID_ARGUMENT);  // one-sided face must be a boundary face
+        }
+    }
+    for (int e = 0; e < ne; ++e)
+        for (int lf = 0; lf < 6; ++lf) {
+            int F = ctx->elem_face[6 * e + lf];
+            if (F < 0 || F >= nf) return fail(HDG_ERR_INVALID_ARGUMENT);
+            bool ok = (ctx->face_elem[4 * F] == e && ctx->face_elem[4 * F + 1] == lf) ||
+                      (ctx->face_elem[4 * F + 2] == e && ctx->face_elem[4 * F + 3] == lf);
+            if (!ok) return fail(HDG_ERR_INVALID_ARGUMENT);
+        }
+    // ---- sizes and offsets
+    ctx->node_off.assign(ne + 1, 0);
+    ctx->E_off.assign(ne + 1, 0);
+    ctx->SK_off.assign(ne + 1, 0);
+    ctx->asm_off.assign(ne + 1, 0);
+    ctx->qp_off.assign(ne + 1, 0);
+    ctx->asmsys_off.assign(ne + 1, 0);
+    ctx->tloc_off.assign(ne + 1, 0);
+    ctx->vgeo_off.assign(ne + 1, 0);
+    ctx->fgeo_off.assign(6 * ne + 1, 0);
+    ctx->toff.assign(7 * ne, 0);
+    ctx->elem_n.resize(ne);
+    ctx->elem_f.resize(ne);
+    ctx->face_off.assign(nf + 1, 0);
+    for (int F = 0; F < nf; ++F) ctx->face_off[F + 1] = ctx->face_off[F] + trace_size(ctx->face_p[F]);
+    for (int e = 0; e < ne; ++e) {
+        int p = ctx->elem_p[e], Np = (p + 1) * (p + 1) * (p + 1), Nq = (p + 2) * (p + 2) * (p + 2);
+        int n = 20 * Np, f = 0, nqf_tot = 0;
+        for (int lf = 0; lf < 6; ++lf) {
+            int pf = ctx->face_p[ctx->elem_face[6 * e + lf]];
+            ctx->toff[7 * e + lf] = f;
+            f += trace_size(pf);
+            int nqf = (pf + 2) * (pf + 2);
+            nqf_tot += nqf;
+            ctx->fgeo_off[6 * e + lf + 1] = ctx->fgeo_off[6 * e + lf] + 4 * nqf;
+        }
+        ctx->toff[7 * e + 6] = f;
+        ctx->elem_n[e] = n;
+        ctx->elem_f[e] = f;
+        if (p != ctx->elem_p[0]) ctx->uniform_p = false;
+        ctx->max_n = std::max(ctx->max_n, n);
+        ctx->max_f = std::max(ctx->max_f, f);
+        ctx->max_p = std::max(ctx->max_p, p);
+        ctx->node_off[e + 1] = ctx->node_off[e] + Np;
+        ctx->E_off[e + 1] = ctx->E_off[e] + (int64_t)(n + f) * hdg::e_ld(n, f);
+        ctx->SK_off[e + 1] = ctx->SK_off[e] + (int64_t)f * (f + 1);
+        ctx->asm_off[e + 1] = ctx->asm_off[e] + (int64_t)f * f;
+        ctx->qp_off[e + 1] = ctx->qp_off[e] + (int64_t)(hdg::kVJac + hdg::kVRes) * Nq + (int64_t)hdg::kFPer * nqf_tot;
+        ctx->vgeo_off[e + 1] = ctx->vgeo_off[e] + 10 * Nq;
+        ctx->asmsys_off[e + 1] = ctx->asmsys_off[e] + (int64_t)(2 * f) * hdg::e_ld(f, f);
+        ctx->tloc_off[e + 1] = ctx->tloc_off[e] + f;
+    }
+    for (int F = 0; F < nf; ++F) ctx->max_b = std::max(ctx->max_b, trace_size(ctx->face_p[F]));
+    // ---- tables and geometry
+    std::vector<double> tbl(hdg::kTblSize);
+    build_tables(tbl.data());
+    std::vector<double> vgeo(ctx->vgeo_off[ne]), fgeo(ctx->fgeo_off[6 * ne]);
+    for (int e = 0; e < ne; ++e) {
+        double X8[24];
+        for (int v = 0; v < 8; ++v)
+            for (int i = 0; i < 3; ++i) X8[3 * v + i] = m->vert_xyz[3 * m->elem_vert[8 * e + v] + i];
+        int p = ctx->elem_p[e], nq = p + 2, Nq = nq * nq * nq;
+        double x[8], w[8];
+        gauss_rule(nq, x, w);
+        double *vg = vgeo.data() + ctx->vgeo_off[e];
+        for (int g2 = 0; g2 < nq; ++g2)
+            for (int g1 = 0; g1 < nq; ++g1)
+                for (int g0 = 0; g0 < nq; ++g0) {
+                    int g = g0 + nq * (g1 + nq * g2);
+                    double xi[3] = {x[g0], x[g1], x[g2]}, J[3][3], G[3][3];
+                    map_jacobian(X8, xi, J);
+                    double det = invert3(J, G);
+                    if (!(det > 0.0)) return fail(HDG_ERR_INVALID_ARGUMENT);
+                    vg[g] = w[g0] * w[g1] * w[g2] * det;
+                    for (int d = 0; d < 3; ++d)
+                        for (int j = 0; j < 3; ++j) vg[(1 + 3 * d + j) * Nq + g] = G[d][j];
+                }
+        for (int lf = 0; lf < 6; ++lf) {
+            int d = lf / 2, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+            double sgn = (lf & 1) ? 1.0 : -1.0;
+            int pf = ctx->face_p[ctx->elem_face[6 * e + lf]], nqf1 = pf + 2, nqf = nqf1 * nqf1;
+            double xf[8], wf[8];
+            gauss_rule(nqf1, xf, wf);
+            double *fg = fgeo.data() + ctx->fgeo_off[6 * e + lf];
+            for (int s1 = 0; s1 < nqf1; ++s1)
+                for (int s0 = 0; s0 < nqf1; ++s0) {
+                    int s = s0 + nqf1 * s1;
+                    double xi[3], J[3][3], G[3][3];
+                    xi[d] = sgn;
+                    xi[t0] = xf[s0];
+                    xi[t1] = xf[s1];
+                    map_jacobian(X8, xi, J);
+                    double det = invert3(J, G);
+                    if (!(det > 0.0)) return fail(HDG_ERR_INVALID_ARGUMENT);
+                    // Nanson: n dS = det J J^{-T} n_ref dS_ref, n_ref = sgn e_d
+                    double N[3] = {sgn * det * G[d][0], sgn * det * G[d][1], sgn * det * G[d][2]};
+                    double ws = wf[s0] * wf[s1];
+                    for (int j = 0; j < 3; ++j) fg[j * nqf + s] = ws * N[j];
+                    fg[3 * nqf + s] = ws * std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+                }
+        }
+    }
+    // an element meeting the same face twice (one element across a periodic
+    // direction) makes its Schwarz patch repeat unknowns
+    for (int e = 0; e < ne; ++e)
+        for (int a = 0; a < 6; ++a)
+            for (int b = a + 1; b < 6; ++b)
+                if (ctx->elem_face[6 * e + a] == ctx->elem_face[6 * e + b]) ctx->repeated_face = true;
+    // ---- block-sparse pattern and gather lists
+    std::vector<std::vector<int>> cols(nf);
+    for (int e = 0; e < ne; ++e)
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) cols[ctx->elem_face[6 * e + a]].push_back(ctx->elem_face[6 * e + b]);
+    ctx->bsr_row_ptr.assign(nf + 1, 0);
+    for (int F = 0; F < nf; ++F) {
+        std::sort(cols[F].begin(), cols[F].end());
+        cols[F].erase(std::unique(cols[F].begin(), cols[F].end()), cols[F].end());
+        ctx->bsr_row_ptr[F + 1] = ctx->bsr_row_ptr[F] + (int)cols[F].size();
+    }
+    int nnzb = ctx->bsr_row_ptr[nf];
+    for (int F = 0; F < nf; ++F)
+        if (ctx->bsr_row_ptr[F + 1] - ctx->bsr_row_ptr[F] > 16) return fail(HDG_ERR_UNSUPPORTED);  // matvec row cache
+    ctx->bsr_col.resize(nnzb);
+    ctx->bsr_val_off.assign(nnzb + 1, 0);
+    for (int F = 0; F < nf; ++F)
+        for (size_t k = 0; k < cols[F].size(); ++k) {
+            int kk = ctx->bsr_row_ptr[F] + (int)k, G = cols[F][k];
+            ctx->bsr_col[kk] = G;
+            ctx->bsr_val_off[kk + 1] = ctx->bsr_val_off[kk] + (int64_t)trace_size(ctx->face_p[F]) * trace_size(ctx->face_p[G]);
+        }
+    auto blk_index = [&](int F, int G) {
+        auto b = ctx->bsr_col.begin() + ctx->bsr_row_ptr[F], en = ctx->bsr_col.begin() + ctx->bsr_row_ptr[F + 1];
+        return (int)(std::lower_bound(b, en, G) - ctx->bsr_col.begin());
+    };
+    std::vector<std::vector<int>> contrib(nnzb);
+    std::vector<int> asm_blk(36 * ne);
+    for (int e = 0; e < ne; ++e)
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+                int k = blk_index(ctx->elem_face[6 * e + a], ctx->elem_face[6 * e + b]);
+                contrib[k].insert(contrib[k].end(), {e, a, b});
+                asm_blk[36 * e + 6 * a + b] = k;
+            }
+    std::vector<int> blk_src_ptr(nnzb + 1, 0), blk_src;
+    for (int k = 0; k < nnzb; ++k) {
+        blk_src_ptr[k + 1] = blk_src_ptr[k] + (int)contrib[k].size() / 3;
+        blk_src.insert(blk_src.end(), contrib[k].begin(), contrib[k].end());
+    }
+    std::vector<int> face_src_ptr(nf + 1, 0), face_src;
+    {
+        std::vector<std::vector<int>> fs(nf);
+        for (int e = 0; e < ne; ++e)
+            for (int a = 0; a < 6; ++a) fs[ctx->elem_face[6 * e + a]].insert(fs[ctx->elem_face[6 * e + a]].end(), {e, a});
+        for (int F = 0; F < nf; ++F) {
+            face_src_ptr[F + 1] = face_src_ptr[F] + (int)fs[F].size() / 2;
+            face_src.insert(face_src.end(), fs[F].begin(), fs[F].end());
+        }
+    }
+    // ---- upload (first HIP call: everything above is host-side validation and set-up)
+    if (hipGetDevice(&ctx->device) != hipSuccess) return fail(HDG_ERR_DEVICE);
+    DevMesh &dm = ctx->dm;
+    dm.n_elem = ne;
+    dm.n_face = nf;
+    int st = HDG_OK;
+#define UP(vec, field) do { if ((st = upload(ctx, vec, &dm.field)) != HDG_OK) return fail(st); } while (0)
+    UP(ctx->elem_p, elem_p);
+    UP(ctx->face_p, face_p);
+    UP(ctx->elem_face, elem_face);
+    UP(ctx->face_bc, face_bc);
+    UP(ctx->toff, toff);
+    UP(ctx->node_off, node_off);
+    UP(ctx->face_off, face_off);
+    UP(ctx->E_off, E_off);
+    UP(ctx->SK_off, SK_off);
+    UP(ctx->asm_off, asm_off);
+    UP(ctx->qp_off, qp_off);
+    UP(ctx->asmsys_off, asmsys_off);
+    UP(ctx->tloc_off, tloc_off);
+    UP(ctx->vgeo_off, vgeo_off);
+    UP(ctx->fgeo_off, fgeo_off);
+    UP(vgeo, vgeo);
+    UP(fgeo, fgeo);
+    UP(tbl, tbl);
+    UP(ctx->bsr_row_ptr, bsr_row_ptr);
+    UP(ctx->bsr_col, bsr_col);
+    UP(ctx->bsr_val_off, bsr_val_off);
+    UP(blk_src_ptr, blk_src_ptr);
+    UP(blk_src, blk_src);
+    UP(face_src_ptr, face_src_ptr);
+    UP(face_src, face_src);
+    UP(asm_blk, asm_blk);
+#undef UP
+    ctx->bsr_row_ptr64.assign(ctx->bsr_row_ptr.begin(), ctx->bsr_row_ptr.end());
+    ctx->bsr_col64.assign(ctx->bsr_col.begin(), ctx->bsr_col.end());
+    *out = ctx;
+    return HDG_OK;
+}
+
+int64_t hdg_layout_length(const hdg_ctx *ctx, int kind) {
+    if (!ctx) return -1;
+    switch (kind) {
+        case HDG_LAYOUT_NODE_OFF: case HDG_LAYOUT_E_OFF: case HDG_LAYOUT_SK_OFF: case HDG_LAYOUT_ASM_OFF:
+            return ctx->n_elem + 1;
+        case HDG_LAYOUT_FACE_OFF: case HDG_LAYOUT_BSR_ROW_PTR: return ctx->n_face + 1;
+        case HDG_LAYOUT_BSR_COL: return (int64_t)ctx->bsr_col.size();
+        case HDG_LAYOUT_BSR_VAL_OFF: return (int64_t)ctx->bsr_val_off.size();
+        case HDG_LAYOUT_ELEM_N: case HDG_LAYOUT_ELEM_F: return ctx->n_elem;
+        default: return -1;
+    }
+}
+
+int hdg_layout(const hdg_ctx *ctx, int kind, int64_t *dst, int64_t capacity) {
+    if (!ctx || !dst) return HDG_ERR_INVALID_ARGUMENT;
+    int64_t len = hdg_layout_length(ctx, kind);
+    if (len < 0 || capacity < len) return HDG_ERR_INVALID_ARGUMENT;
+    const std::vector<int64_t> *v = nullptr;
+    switch (kind) {
+        case HDG_LAYOUT_NODE_OFF: v = &ctx->node_off; break;
+        case HDG_LAYOUT_FACE_OFF: v = &ctx->face_off; break;
+        case HDG_LAYOUT_E_OFF: v = &ctx->E_off; break;
+        case HDG_LAYOUT_SK_OFF: v = &ctx->SK_off; break;
+        case HDG_LAYOUT_ASM_OFF: v = &ctx->asm_off; break;
+        case HDG_LAYOUT_BSR_ROW_PTR: v = &ctx->bsr_row_ptr64; break;
+        case HDG_LAYOUT_BSR_COL: v = &ctx->bsr_col64; break;
+        case HDG_LAYOUT_BSR_VAL_OFF: v = &ctx->bsr_val_off; break;
+        case HDG_LAYOUT_ELEM_N:
+            for (int e = 0; e < ctx->n_elem; ++e) dst[e] = ctx->elem_n[e];
+            return HDG_OK;
+        case HDG_LAYOUT_ELEM_F:
+            for (int e = 0; e < ctx->n_elem; ++e) dst[e] = ctx->elem_f[e];
+            return HDG_OK;
+    }
+    std::copy(v->begin(), v->end(), dst);
+    return HDG_OK;
+}
+
+static bool chunk_ok(const hdg_ctx *ctx, int e0, int ne) {
+    return ctx && e0 >= 0 && ne >= 1 && (int64_t)e0 + ne <= ctx->n_elem;
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, size_t *bytes) {
+    if (!ctx || !bytes || (prec != HDG_FP64 && prec != HDG_MIXED)) return HDG_ERR_INVALID_ARGUMENT;
+    switch (op) {
+        case 0:  // hdg_local_residual_jacobian
+            if (!chunk_ok(ctx, e0, ne)) return HDG_ERR_INVALID_ARGUMENT;
+            *bytes = round256(sizeof(double) * (size_t)(ctx->qp_off[e0 + ne] - ctx->qp_off[e0]));
+            return HDG_OK;
+        case 1:  // hdg_condense
+            if (!chunk_ok(ctx, e0, ne)) return HDG_ERR_INVALID_ARGUMENT;
+            *bytes = (prec == HDG_FP64) ? round256(hdg::bordered_lu_work(ctx, ne))
+                                        : hdg::condense_mixed_work_bytes(ctx, e0, ne);
+            return HDG_OK;
+        case 2: *bytes = hdg::asm_setup_work_bytes(ctx); return HDG_OK;
+        case 3: *bytes = hdg::asm_apply_work_bytes(ctx); return HDG_OK;
+        case 4:
+            if (ne < 1 || ne > 200) return HDG_ERR_INVALID_ARGUMENT;
+            *bytes = hdg::gmres_work_bytes(ctx, ne);
+            return HDG_OK;
+        default: return HDG_ERR_INVALID_ARGUMENT;
+    }
+}
+
+static int dev_status(int hip_err) { return hip_err == 0 ? HDG_OK : HDG_ERR_DEVICE; }
+
+int hdg_local_residual_jacobian(hdg_ctx *ctx, int e0, int ne, const double *Q, const double *U,
+                                const double *Un, const double *Uhat, const double *nu, const double *Ub,
+                                double *E, void *work, size_t work_bytes, void *stream) {
+    if (!chunk_ok(ctx, e0, ne) || !Q || !U || !Un || !Uhat || !nu || !E || !work) return HDG_ERR_INVALID_ARGUMENT;
+    for (int e = e0; e < e0 + ne; ++e)
+        for (int lf = 0; lf < 6; ++lf)
+            if (ctx->face_bc[ctx->elem_face[6 * e + lf]] && !Ub) return HDG_ERR_INVALID_ARGUMENT;
+    size_t need;
+    hdg_workspace_size(ctx, 0, HDG_FP64, e0, ne, &need);
+    if (work_bytes < need) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_element_system(ctx, e0, ne, Q, U, Un, Uhat, nu, Ub, E, (double *)work,
+                                                 (hipStream_t)stream));
+}
+
+int hdg_condense(hdg_ctx *ctx, int prec, int refine_steps, int e0, int ne, double *E, double *SK, int *info,
+                 void *work, size_t work_bytes, void *stream) {
+    if (!chunk_ok(ctx, e0, ne) || !E || !SK || !info) return HDG_ERR_INVALID_ARGUMENT;
+    if (prec != HDG_FP64 && prec != HDG_MIXED) return HDG_ERR_INVALID_ARGUMENT;
+    if (prec == HDG_MIXED && (refine_steps < 1 || refine_steps > 8)) return HDG_ERR_INVALID_ARGUMENT;
+    size_t need;
+    hdg_workspace_size(ctx, 1, prec, e0, ne, &need);
+    if (!work || work_bytes < need) return HDG_ERR_WORKSPACE;
+    if (prec == HDG_FP64)
+        return dev_status(hdg::launch_condense_fp64(ctx, e0, ne, E, SK, info, work, (hipStream_t)stream));
+    return dev_status(hdg::launch_condense_mixed(ctx, e0, ne, refine_steps, E, SK, info, work, (hipStream_t)stream));
+}
+
+int hdg_assemble_trace(hdg_ctx *ctx, const double *SK, double *S_bsr, double *g, void *stream) {
+    if (!ctx || !SK || !S_bsr || !g) return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_assemble(ctx, SK, S_bsr, g, (hipStream_t)stream));
+}
+
+int hdg_face_matvec(hdg_ctx *ctx, const double *S_bsr, const double *x, double *y, void *stream) {
+    if (!ctx || !S_bsr || !x || !y || x == y) return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_matvec(ctx, S_bsr, x, y, (hipStream_t)stream));
+}
+
+int hdg_asm_setup(hdg_ctx *ctx, int prec, const double *S_bsr, void *Sinv, int *info, void *work,
+                  size_t work_bytes, void *stream) {
+    if (!ctx || !S_bsr || !Sinv || !info || (prec != HDG_FP64 && prec != HDG_MIXED)) return HDG_ERR_INVALID_ARGUMENT;
+    if (ctx->repeated_face) return HDG_ERR_UNSUPPORTED;
+    if (work_bytes < hdg::asm_setup_work_bytes(ctx) || !work) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_asm_setup(ctx, prec, S_bsr, Sinv, info, work, (hipStream_t)stream));
+}
+
+int hdg_asm_block_apply(hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z, void *work,
+                        size_t work_bytes, void *stream) {
+    if (!ctx || !Sinv || !r || !z || r == z || (prec != HDG_FP64 && prec != HDG_MIXED)) return HDG_ERR_INVALID_ARGUMENT;
+    if (work_bytes < hdg::asm_apply_work_bytes(ctx) || !work) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_asm_apply(ctx, prec, Sinv, r, z, work, (hipStream_t)stream));
+}
+
+int hdg_gmres(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, const double *g, int m,
+              double *dUhat, double *res_hist, void *work, size_t work_bytes, void *stream) {
+    if (!ctx || !S_bsr || !Sinv || !g || !dUhat || !res_hist || m < 1 || m > 200 ||
+        (prec != HDG_FP64 && prec != HDG_MIXED))
+        return HDG_ERR_INVALID_ARGUMENT;
+    if (work_bytes < hdg::gmres_work_bytes(ctx, m) || !work) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_gmres(ctx, prec, S_bsr, Sinv, g, m, dUhat, res_hist, work, (hipStream_t)stream));
+}
+
+int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E, const double *dUhat,
+                         double *dQU, void *stream) {
+    if (!chunk_ok(ctx, e0, ne) || !E || !dUhat || !dQU || (prec != HDG_FP64 && prec != HDG_MIXED))
+        return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_recover(ctx, prec, e0, ne, E, dUhat, dQU, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations of libhdg: context, device tables, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/hdg.h"
+
+namespace hdg {
+
+constexpr int kMaxP = 4;
+
+// ---------------------------------------------------------------- 1-D tables
+// Lagrange polynomials of the Gauss-Lobatto nodes evaluated at Gauss points:
+//   L(p, q, a, s) = l^p_a(x^{q+2}_s)     p, q in 1..4 (basis degree, rule of degree q)
+//   D(p, a, g)    = (l^p_a)'(x^{p+2}_g)
+//   W(nq, g)      = Gauss weight, nq in 3..6
+constexpr int kTblL = 0;
+constexpr int kTblD = kTblL + 16 * 30;
+constexpr int kTblW = kTblD + 4 * 30;
+constexpr int kTblSize = kTblW + 4 * 6;
+__host__ __device__ inline int tbl_L(int p, int q, int a, int s) { return kTblL + ((p - 1) * 4 + (q - 1)) * 30 + a * 6 + s; }
+__host__ __device__ inline int tbl_D(int p, int a, int g) { return kTblD + (p - 1) * 30 + a * 6 + g; }
+__host__ __device__ inline int tbl_W(int nq, int g) { return kTblW + (nq - 3) * 6 + g; }
+
+// Per-element quadrature-point data written by the point kernels (doubles):
+//   volume  vjac [c 5][s 20][d 4][g]   coefficient of phi_k and of the reference
+//                                      derivatives of phi_i in row u_c, column field s
+//           vres [r 20][d 4][g]        residual coefficients of row field r
+//   face lf (lf = 0..5, points of that face)
+//           fjac [c 5][slot 25][s]     d(fh_c dS)/d(u 0..4, q 5..19, uh 20..24), weights included
+//           fres [c 5][s]              fh_c dS
+//           bres [c 5][s]              |N| w (uh - ub)_c   (Dirichlet faces)
+//           fuh  [c 5][s]              uh_c
+constexpr int kVJac = 400, kVRes = 80, kFJac = 125, kFPer = 140;
+
+// Device view of a context, passed by value to kernels.
+struct DevMesh {
+    int n_elem, n_face;
+    const int *elem_p;         // [n_elem]
+    const int *face_p;         // [n_face]
+    const int *elem_face;      // [n_elem][6]
+    const int *face_bc;        // [n_face]
+    const int *toff;           // [n_elem][7] element-local trace offsets per local face
+    const int64_t *node_off;   // [n_elem+1]
+    const int64_t *face_off;   // [n_face+1]
+    const int64_t *E_off;      // [n_elem+1]
+    const int64_t *SK_off;     // [n_elem+1]
+    const int64_t *asm_off;    // [n_elem+1]
+    const int64_t *qp_off;     // [n_elem+1]
+    const int64_t *asmsys_off; // [n_elem+1] Schwarz inversion systems (2f x ld doubles)
+    const int64_t *tloc_off;   // [n_elem+1] prefix sums of f_e (element-local trace vectors)
+    const int64_t *vgeo_off;   // [n_elem+1]  volume geometry: [10][Nq] = W, G00..G22 (G = J^{-1})
+    const int64_t *fgeo_off;   // [n_elem*6+1] face geometry: [4][Nqf] = w N_x, w N_y, w N_z, w |N|
+    const double *vgeo;
+    const double *fgeo;
+    const double *tbl;         // kTblSize doubles
+    // block-sparse trace operator
+    const int *bsr_row_ptr;    // [n_face+1]
+    const int *bsr_col;        // [nnzb]
+    const int64_t *bsr_val_off;// [nnzb+1]
+    const int *blk_src_ptr;    // [nnzb+1] contributions to each block
+    const int *blk_src;        // [n][3]: elem, local face a (row), local face b (col)
+    const int *face_src_ptr;   // [n_face+1] elements touching each face
+    const int *face_src;       // [n][2]: elem, local face
+    const int *asm_blk;        // [n_elem][36]: bsr block index of (face a, face b)
+};
+
+struct Phys {
+    double gamma, prandtl, reynolds, mach, tau, dt, alpha;
+    int visc_law;
+};
+
+// Element-system row stride (doubles): n + f + 1 rounded up to a multiple of 8.
+__host__ __device__ inline int64_t e_ld(int n, int f) { return ((int64_t)(n + f + 1) + 7) / 8 * 8; }
+
+}  // namespace hdg
+
+struct hdg_ctx {
+    int device = 0;
+    int n_elem = 0, n_face = 0;
+    hdg::Phys phys{};
+    int max_n = 0, max_f = 0, max_b = 0, max_p = 0;
+    bool uniform_p = true;
+    bool repeated_face = false;  // some element meets the same face twice
+    std::vector<int> elem_p, face_p, elem_face, face_elem, face_bc, toff, elem_n, elem_f;
+    std::vector<int64_t> node_off, face_off, E_off, SK_off, asm_off, qp_off, vgeo_off, fgeo_off, asmsys_off,
+        tloc_off;
+    std::vector<int64_t> bsr_row_ptr64, bsr_col64, bsr_val_off;
+    std::vector<int> bsr_row_ptr, bsr_col;
+    hdg::DevMesh dm{};
+    std::vector<void *> allocations;  // device buffers owned by the context
+};
+
+namespace hdg {
+// kernel launchers (return hipError_t as int)
+int launch_element_system(const hdg_ctx *ctx, int e0, int ne, const double *Q, const double *U,
+                          const double *Un, const double *Uhat, const double *nu, const double *Ub,
+                          double *E, double *qp, hipStream_t s);
+int launch_condense_fp64(const hdg_ctx *ctx, int e0, int ne, double *E, double *SK, int *info,
+                         void *work, hipStream_t s);
+int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double *E, double *SK,
+                          int *info, void *work, hipStream_t s);
+size_t condense_mixed_work_bytes(const hdg_ctx *ctx, int e0, int ne);
+size_t bordered_lu_work(const hdg_ctx *ctx, int ne);
+int run_asm_inversion(const hdg_ctx *ctx, double *sys, int *info, void *work, hipStream_t s);
+int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, hipStream_t s);
+int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *y, hipStream_t s);
+int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info,
+                     void *work, hipStream_t s);
+size_t asm_setup_work_bytes(const hdg_ctx *ctx);
+int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
+                     void *work, hipStream_t s);
+size_t asm_apply_work_bytes(const hdg_ctx *ctx);
+int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv, const double *g,
+                 int m, double *x, double *hist, void *work, hipStream_t s);
+size_t gmres_work_bytes(const hdg_ctx *ctx, int m);
+int launch_recover(const hdg_ctx *ctx, int prec, int e0, int ne, const double *E,
+                   const double *dUhat, double *dQU, hipStream_t s);
+}  // namespace hdg

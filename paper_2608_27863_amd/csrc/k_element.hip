@@ -1,0 +1,599 @@
+// Element residuals and Jacobian blocks of the HDG discretisation.
+//
+// Two stages (the quadrature-point kernels feed the assembly kernel through a
+// workspace, as in the paper's split of pointwise kernels and assembly
+// kernels that look like batched linear algebra):
+//   k_qp_volume / k_qp_face : interpolate (u, u^n, q, nu) to the Gauss points,
+//       evaluate the fluxes of eqs. convective-flux, viscous-flux, stress-heat,
+//       av-total and the numerical flux of eq. num-flux-hdg, and their exact
+//       Jacobians (derived by hand below), already multiplied by quadrature
+//       weights, the geometric factors and dt / alpha;
+//   k_assemble_rows : contract the point coefficients with the basis
+//       (phi_i, reference derivatives of phi_i, phi_k, trace basis mu_a) into
+//       the rows of the element system E^K = [[A B R_qu],[C D R_uh]].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "hdg_internal.h"
+
+namespace hdg {
+namespace {
+
+// ------------------------------------------------------------------ physics
+// Intermediates at one point for state w and conservative gradient q.
+struct PState {
+    double rho, v[3], E, mus, kap, dmus[5];
+    double dv[3][3], dE[3], de[3], S[3][3];
+    double vv;  // |v|^2
+};
+
+__device__ inline void pstate(const double *w, const double *q, const Phys &P, PState &s) {
+    const double rho = w[0], ir = 1.0 / rho;
+    s.rho = rho;
+    for (int i = 0; i < 3; ++i) s.v[i] = w[1 + i] * ir;
+    s.E = w[4] * ir;
+    s.vv = s.v[0] * s.v[0] + s.v[1] * s.v[1] + s.v[2] * s.v[2];
+    const double e = s.E - 0.5 * s.vv;
+    const double cT = P.gamma * (P.gamma - 1.0) * P.mach * P.mach;
+    double mu = 1.0, dmu = 0.0;
+    if (P.visc_law == 1) {
+        const double T = cT * e, sq = sqrt(T), den = 1.0 / (T + 0.40417);
+        mu = 1.4042 * T * sq * den;
+        // d/dT [c1 T^{3/2} / (T + c2)] = c1 sqrt(T) (T/2 + 3 c2 / 2) / (T + c2)^2
+        dmu = 1.4042 * sq * (0.5 * T + 1.5 * 0.40417) * den * den;
+    }
+    s.mus = mu / P.reynolds;
+    s.kap = P.gamma * s.mus / P.prandtl;
+    // de/dw = ((|v|^2 - E)/rho, -v/rho, 1/rho)
+    const double dedw[5] = {(s.vv - s.E) * ir, -s.v[0] * ir, -s.v[1] * ir, -s.v[2] * ir, ir};
+    for (int c = 0; c < 5; ++c) s.dmus[c] = dmu * cT * dedw[c] / P.reynolds;
+    for (int j = 0; j < 3; ++j) {
+        for (int i = 0; i < 3; ++i) s.dv[i][j] = (q[3 * (1 + i) + j] - s.v[i] * q[j]) * ir;
+        s.dE[j] = (q[12 + j] - s.E * q[j]) * ir;
+        s.de[j] = s.dE[j] - (s.v[0] * s.dv[0][j] + s.v[1] * s.dv[1][j] + s.v[2] * s.dv[2][j]);
+    }
+    const double div = s.dv[0][0] + s.dv[1][1] + s.dv[2][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) s.S[i][j] = s.dv[i][j] + s.dv[j][i] - (i == j ? (2.0 / 3.0) * div : 0.0);
+}
+
+// F = F^c(w) - F^v(w, q) - nu q   (total flux entering the residuals)
+__device__ inline void total_flux(const double *w, const double *q, double nu, const Phys &P,
+                                  const PState &s, double F[5][3]) {
+    const double p = (P.gamma - 1.0) * (w[4] - 0.5 * s.rho * s.vv);
+    for (int j = 0; j < 3; ++j) {
+        F[0][j] = w[1 + j];
+        double tv = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            const double tau = s.mus * s.S[i][j];
+            F[1 + i][j] = w[1 + i] * s.v[j] + (i == j ? p : 0.0) - tau;
+            tv += s.v[i] * tau;
+        }
+        F[4][j] = (w[4] + p) * s.v[j] - tv - s.kap * s.de[j];
+        for (int c = 0; c < 5; ++c) F[c][j] -= nu * q[3 * c + j];
+    }
+}
+
+// dF/dw_cp (q fixed) of F = F^c - F^v; nu q does not depend on w.
+__device__ inline void dflux_dw(const double *w, const double *q, const Phys &P, const PState &s,
+                                int cp, double dF[5][3]) {
+    const double ir = 1.0 / s.rho, gm1 = P.gamma - 1.0;
+    const double p = gm1 * (w[4] - 0.5 * s.rho * s.vv);
+    double dp, dvel[3];
+    if (cp == 0) {
+        dp = gm1 * 0.5 * s.vv;
+        for (int i = 0; i < 3; ++i) dvel[i] = -s.v[i] * ir;
+    } else if (cp < 4) {
+        dp = -gm1 * s.v[cp - 1];
+        for (int i = 0; i < 3; ++i) dvel[i] = (i == cp - 1) ? ir : 0.0;
+    } else {
+        dp = gm1;
+        for (int i = 0; i < 3; ++i) dvel[i] = 0.0;
+    }
+    // derivatives of the primitive gradients
+    double ddv[3][3], ddE[3], dde[3];
+    for (int j = 0; j < 3; ++j) {
+        const double q0 = q[j];
+        for (int i = 0; i < 3; ++i) {
+            if (cp == 0) ddv[i][j] = (s.v[i] * q0 * ir - s.dv[i][j]) * ir;
+            else if (cp == 1 + i) ddv[i][j] = -q0 * ir * ir;
+            else ddv[i][j] = 0.0;
+        }
+        if (cp == 0) ddE[j] = (s.E * q0 * ir - s.dE[j]) * ir;
+        else if (cp == 4) ddE[j] = -q0 * ir * ir;
+        else ddE[j] = 0.0;
+        dde[j] = ddE[j];
+        for (int i = 0; i < 3; ++i) dde[j] -= dvel[i] * s.dv[i][j] + s.v[i] * ddv[i][j];
+    }
+    const double ddiv = ddv[0][0] + ddv[1][1] + ddv[2][2];
+    const double dmus = s.dmus[cp], dkap = P.gamma * dmus / P.prandtl;
+    for (int j = 0; j < 3; ++j) {
+        // convective part
+        dF[0][j] = (cp == 1 + j) ? 1.0 : 0.0;
+        for (int i = 0; i < 3; ++i)
+            dF[1 + i][j] = ((cp == 1 + i) ? s.v[j] : 0.0) + s.rho * s.v[i] * dvel[j] + (i == j ? dp : 0.0);
+        dF[4][j] = ((cp == 4 ? 1.0 : 0.0) + dp) * s.v[j] + (w[4] + p) * dvel[j];
+        // viscous part
+        double dvt = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            const double dS = ddv[i][j] + ddv[j][i] - (i == j ? (2.0 / 3.0) * ddiv : 0.0);
+            const double dtau = dmus * s.S[i][j] + s.mus * dS;
+            dF[1 + i][j] -= dtau;
+            dvt += dvel[i] * s.mus * s.S[i][j] + s.v[i] * dtau;
+        }
+        dF[4][j] -= dvt + dkap * s.de[j] + s.kap * dde[j];
+    }
+}
+
+// dF^v/dq_{cpp,l} including nu q (F^v is linear in q).
+__device__ inline void dfv_dq(const PState &s, double nu, int cpp, int l, double dF[5][3]) {
+    const double ir = 1.0 / s.rho;
+    double b[3];
+    for (int i = 0; i < 3; ++i) b[i] = (((cpp == 1 + i) ? 1.0 : 0.0) - (cpp == 0 ? s.v[i] : 0.0)) * ir;
+    double a = 0.0;
+    if (cpp == 4) a = ir;
+    else if (cpp == 0) a = (s.vv - s.E) * ir;
+    else a = -s.v[cpp - 1] * ir;
+    const double vb = s.v[0] * b[0] + s.v[1] * b[1] + s.v[2] * b[2];
+    for (int j = 0; j < 3; ++j) {
+        const double djl = (j == l) ? 1.0 : 0.0;
+        dF[0][j] = (cpp == 0) ? nu * djl : 0.0;
+        for (int i = 0; i < 3; ++i)
+            dF[1 + i][j] = s.mus * (djl * b[i] + (i == l ? b[j] : 0.0) - (i == j ? (2.0 / 3.0) * b[l] : 0.0)) +
+                           ((cpp == 1 + i) ? nu * djl : 0.0);
+        dF[4][j] = s.mus * (djl * vb + s.v[l] * b[j] - (2.0 / 3.0) * s.v[j] * b[l]) + s.kap * djl * a +
+                   ((cpp == 4) ? nu * djl : 0.0);
+    }
+}
+
+__device__ inline int64_t qp_face_base(const DevMesh &dm, int e, int lf, int Nq) {
+    int64_t off = dm.qp_off[e] + (int64_t)(kVJac + kVRes) * Nq;
+    for (int l = 0; l < lf; ++l) {
+        const int pf = dm.face_p[dm.elem_face[6 * e + l]];
+        off += (int64_t)kFPer * (pf + 2) * (pf + 2);
+    }
+    return off;
+}
+
+// ------------------------------------------------------- point kernel: volume
+__global__ void __launch_bounds__(256) k_qp_volume(DevMesh dm, Phys P, int e0, const double *__restrict__ Qg,
+                                                   const double *__restrict__ Ug, const double *__restrict__ Ung,
+                                                   const double *__restrict__ nug, double *__restrict__ qp) {
+    const int e = e0 + blockIdx.x;
+    const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
+    __shared__ double sU[5 * 125], sUn[5 * 125], sQ[15 * 125], sNu[125], sL[5 * 6];
+    const int64_t no = dm.node_off[e];
+    for (int t = threadIdx.x; t < 5 * Np; t += blockDim.x) {
+        sU[t] = Ug[5 * no + t];
+        sUn[t] = Ung[5 * no + t];
+    }
+    for (int t = threadIdx.x; t < 15 * Np; t += blockDim.x) sQ[t] = Qg[15 * no + t];
+    for (int t = threadIdx.x; t < Np; t += blockDim.x) sNu[t] = nug[no + t];
+    for (int t = threadIdx.x; t < p1 * nq; t += blockDim.x) sL[t] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
+    __syncthreads();
+    const double *vg = dm.vgeo + dm.vgeo_off[e];
+    double *out = qp + (dm.qp_off[e] - dm.qp_off[e0]);
+    for (int g = threadIdx.x; g < Nq; g += blockDim.x) {
+        const int g0 = g % nq, g1 = (g / nq) % nq, g2 = g / (nq * nq);
+        double u[5] = {0, 0, 0, 0, 0}, un[5] = {0, 0, 0, 0, 0}, q[15], nu = 0.0;
+        for (int m = 0; m < 15; ++m) q[m] = 0.0;
+        for (int i2 = 0; i2 < p1; ++i2)
+            for (int i1 = 0; i1 < p1; ++i1) {
+                const double l12 = sL[i1 * nq + g1] * sL[i2 * nq + g2];
+                for (int i0 = 0; i0 < p1; ++i0) {
+                    const double ph = sL[i0 * nq + g0] * l12;
+                    const int i = i0 + p1 * (i1 + p1 * i2);
+                    for (int c = 0; c < 5; ++c) {
+                        u[c] += ph * sU[c * Np + i];
+                        un[c] += ph * sUn[c * Np + i];
+                    }
+                    for (int m = 0; m < 15; ++m) q[m] += ph * sQ[m * Np + i];
+                    nu += ph * sNu[i];
+                }
+            }
+        const double W = vg[g];
+        double G[3][3];
+        for (int d = 0; d < 3; ++d)
+            for (int j = 0; j < 3; ++j) G[d][j] = vg[(1 + 3 * d + j) * Nq + g];
+        PState s;
+        pstate(u, q, P, s);
+        double F[5][3];
+        total_flux(u, q, nu, P, s, F);
+        double *vres = out + (int64_t)kVJac * Nq;
+        // residual coefficients: gradient rows
+        for (int c = 0; c < 5; ++c)
+            for (int j = 0; j < 3; ++j) {
+                const int r = 3 * c + j;
+                vres[(4 * r + 0) * Nq + g] = W * q[r];
+                for (int d = 0; d < 3; ++d) vres[(4 * r + 1 + d) * Nq + g] = W * u[c] * G[d][j];
+            }
+        // residual coefficients: conservation rows
+        for (int c = 0; c < 5; ++c) {
+            const int r = 15 + c;
+            vres[(4 * r + 0) * Nq + g] = P.alpha * W * (u[c] - un[c]);
+            for (int d = 0; d < 3; ++d)
+                vres[(4 * r + 1 + d) * Nq + g] = -P.dt * W * (G[d][0] * F[c][0] + G[d][1] * F[c][1] + G[d][2] * F[c][2]);
+        }
+        // Jacobian coefficients of the conservation rows
+        for (int cp = 0; cp < 5; ++cp) {
+            double dF[5][3];
+            dflux_dw(u, q, P, s, cp, dF);
+            for (int c = 0; c < 5; ++c) {
+                const int sidx = 15 + cp;
+                double *o = out + (int64_t)(4 * (20 * c + sidx)) * Nq + g;
+                o[0] = (c == cp) ? P.alpha * W : 0.0;
+                for (int d = 0; d < 3; ++d)
+                    o[(1 + d) * Nq] = -P.dt * W * (G[d][0] * dF[c][0] + G[d][1] * dF[c][1] + G[d][2] * dF[c][2]);
+            }
+        }
+        for (int m = 0; m < 15; ++m) {
+            double dF[5][3];
+            dfv_dq(s, nu, m / 3, m % 3, dF);
+            for (int c = 0; c < 5; ++c) {
+                double *o = out + (int64_t)(4 * (20 * c + m)) * Nq + g;
+                o[0] = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    o[(1 + d) * Nq] = P.dt * W * (G[d][0] * dF[c][0] + G[d][1] * dF[c][1] + G[d][2] * dF[c][2]);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------- point kernel: face
+__global__ void __launch_bounds__(64) k_qp_face(DevMesh dm, Phys P, int e0, const double *__restrict__ Qg,
+                                                const double *__restrict__ Ug, const double *__restrict__ Uhg,
+                                                const double *__restrict__ nug, const double *__restrict__ Ubg,
+                                                double *__restrict__ qp) {
+    const int lf = blockIdx.x, e = e0 + blockIdx.y;
+    const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
+    const int F = dm.elem_face[6 * e + lf], pf = dm.face_p[F], pf1 = pf + 1, nqf1 = pf + 2, Nqf = nqf1 * nqf1;
+    const int Nfp = pf1 * pf1, bc = dm.face_bc[F];
+    const int d = lf / 2, side = lf & 1, t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+    const int64_t no = dm.node_off[e];
+    const double *fg = dm.fgeo + dm.fgeo_off[6 * e + lf];
+    double *out = qp + (qp_face_base(dm, e, lf, Nq) - dm.qp_off[e0]);
+    const double *uh_g = Uhg + dm.face_off[F];
+    const double *ub_g = bc ? Ubg + dm.face_off[F] : nullptr;
+    for (int s = threadIdx.x; s < Nqf; s += blockDim.x) {
+        const int s0 = s % nqf1, s1 = s / nqf1;
+        double u[5] = {0, 0, 0, 0, 0}, q[15], nu = 0.0, uh[5] = {0, 0, 0, 0, 0}, ub[5] = {0, 0, 0, 0, 0};
+        for (int m = 0; m < 15; ++m) q[m] = 0.0;
+        // element fields: only the nodes on this face are nonzero there
+        for (int a1 = 0; a1 < p1; ++a1)
+            for (int a0 = 0; a0 < p1; ++a0) {
+                const double ph = dm.tbl[tbl_L(p, pf, a0, s0)] * dm.tbl[tbl_L(p, pf, a1, s1)];
+                int idx[3];
+                idx[d] = side ? p : 0;
+                idx[t0] = a0;
+                idx[t1] = a1;
+                const int i = idx[0] + p1 * (idx[1] + p1 * idx[2]);
+                for (int c = 0; c < 5; ++c) u[c] += ph * Ug[5 * no + c * Np + i];
+                for (int m = 0; m < 15; ++m) q[m] += ph * Qg[15 * no + m * Np + i];
+                nu += ph * nug[no + i];
+            }
+        for (int b1 = 0; b1 < pf1; ++b1)
+            for (int b0 = 0; b0 < pf1; ++b0) {
+                const double mu = dm.tbl[tbl_L(pf, pf, b0, s0)] * dm.tbl[tbl_L(pf, pf, b1, s1)];
+                const int b = b0 + pf1 * b1;
+                for (int c = 0; c < 5; ++c) {
+                    uh[c] += mu * uh_g[c * Nfp + b];
+                    if (bc) ub[c] += mu * ub_g[c * Nfp + b];
+                }
+            }
+        const double wN[3] = {fg[s], fg[Nqf + s], fg[2 * Nqf + s]}, wA = fg[3 * Nqf + s];
+        PState st;
+        pstate(uh, q, P, st);
+        double Fl[5][3];
+        total_flux(uh, q, nu, P, st, Fl);
+        for (int c = 0; c < 5; ++c) {
+            out[(125 + c) * Nqf + s] = Fl[c][0] * wN[0] + Fl[c][1] * wN[1] + Fl[c][2] * wN[2] + P.tau * wA * (u[c] - uh[c]);
+            out[(130 + c) * Nqf + s] = bc ? wA * (uh[c] - ub[c]) : 0.0;
+            out[(135 + c) * Nqf + s] = uh[c];
+        }
+        // d fh / d u (element trace): tau |N| I
+        for (int c = 0; c < 5; ++c)
+            for (int cp = 0; cp < 5; ++cp) out[(25 * c + cp) * Nqf + s] = (c == cp) ? P.tau * wA : 0.0;
+        // d fh / d q
+        for (int m = 0; m < 15; ++m) {
+            double dF[5][3];
+            dfv_dq(st, nu, m / 3, m % 3, dF);
+            for (int c = 0; c < 5; ++c)
+                out[(25 * c + 5 + m) * Nqf + s] = -(dF[c][0] * wN[0] + dF[c][1] * wN[1] + dF[c][2] * wN[2]);
+        }
+        // d fh / d uh
+        for (int cp = 0; cp < 5; ++cp) {
+            double dF[5][3];
+            dflux_dw(uh, q, P, st, cp, dF);
+            for (int c = 0; c < 5; ++c)
+                out[(25 * c + 20 + cp) * Nqf + s] =
+                    dF[c][0] * wN[0] + dF[c][1] * wN[1] + dF[c][2] * wN[2] - ((c == cp) ? P.tau * wA : 0.0);
+        }
+    }
+}
+
+// --------------------------------------------------------- assembly kernel
+// Reference-element helpers working on LDS copies of the 1-D tables.
+struct Ref {
+    int p, p1, nq, Np, Nq;
+    const double *L;   // [a][g] values at the volume Gauss points
+    const double *D;   // [a][g] derivatives
+    __device__ inline double phi(int i, int g) const {
+        const int i0 = i % p1, i1 = (i / p1) % p1, i2 = i / (p1 * p1);
+        const int g0 = g % nq, g1 = (g / nq) % nq, g2 = g / (nq * nq);
+        return L[i0 * nq + g0] * L[i1 * nq + g1] * L[i2 * nq + g2];
+    }
+    // value (d = 0) or reference derivative d-1 of phi_i at point g
+    __device__ inline void phi_all(int i, int g, double out[4]) const {
+        const int i0 = i % p1, i1 = (i / p1) % p1, i2 = i / (p1 * p1);
+        const int g0 = g % nq, g1 = (g / nq) % nq, g2 = g / (nq * nq);
+        const double l0 = L[i0 * nq + g0], l1 = L[i1 * nq + g1], l2 = L[i2 * nq + g2];
+        out[0] = l0 * l1 * l2;
+        out[1] = D[i0 * nq + g0] * l1 * l2;
+        out[2] = l0 * D[i1 * nq + g1] * l2;
+        out[3] = l0 * l1 * D[i2 * nq + g2];
+    }
+};
+
+// Face of an element: is volume node i on local face lf, and its face indices.
+__device__ inline bool on_face(int i, int p1, int lf, int &a0, int &a1) {
+    const int d = lf / 2, side = lf & 1;
+    int idx[3] = {i % p1, (i / p1) % p1, i / (p1 * p1)};
+    if (idx[d] != (side ? p1 - 1 : 0)) return false;
+    const int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+    a0 = idx[t0];
+    a1 = idx[t1];
+    return true;
+}
+
+constexpr int kCh = 32;  // quadrature points per LDS chunk
+
+template <int T>
+__global__ void __launch_bounds__(256) k_assemble_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
+                                                       double *__restrict__ Ebase) {
+    const int e = e0 + blockIdx.y;
+    const int rb = blockIdx.x;  // 0..19 interior row field, 20..25 trace rows of face rb-20
+    const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
+    const int *toff = dm.toff + 7 * e;
+    const int n = 20 * Np, f = toff[6];
+    const int64_t ld = e_ld(n, f);
+    double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    const double *qpe = qp + (dm.qp_off[e] - dm.qp_off[e0]);
+    const double *vg = dm.vgeo + dm.vgeo_off[e];
+    const int tid = threadIdx.x;
+
+    __shared__ double sL[30], sD[30];
+    __shared__ double sLf[6][30], sMf[6][30];  // element basis / trace basis at each face's points
+    __shared__ int sPf[6], sNqf[6];
+    __shared__ int64_t sFbase[6];
+    __shared__ double sH[128 * kCh], sP[128 * kCh];
+    __shared__ double sFc[6 * 36];           // face coefficient of the current block
+    __shared__ double sFB[6 * 5 * 36];        // face coefficients of the B columns
+    for (int t = tid; t < p1 * nq; t += blockDim.x) {
+        sL[t] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
+        sD[t] = dm.tbl[tbl_D(p, t / nq, t % nq)];
+    }
+    if (tid < 6) {
+        const int pf = dm.face_p[dm.elem_face[6 * e + tid]];
+        sPf[tid] = pf;
+        sNqf[tid] = (pf + 2) * (pf + 2);
+        sFbase[tid] = qp_face_base(dm, e, tid, Nq) - dm.qp_off[e];
+    }
+    __syncthreads();
+    for (int t = tid; t < 6 * 30; t += blockDim.x) {
+        const int lf = t / 30, r = t % 30, pf = sPf[lf], nqf1 = pf + 2;
+        const int a = r / nqf1, s = r % nqf1;
+        sLf[lf][r] = (a <= p && s < nqf1 && r < (p + 1) * nqf1) ? dm.tbl[tbl_L(p, pf, a, s)] : 0.0;
+        sMf[lf][r] = (a <= pf && r < (pf + 1) * nqf1) ? dm.tbl[tbl_L(pf, pf, a, s)] : 0.0;
+    }
+    __syncthreads();
+    Ref R{p, p1, nq, Np, Nq, sL, sD};
+
+    // value of the element basis phi_i at point s of face lf (i on that face)
+    auto phi_face = [&](int lf, int a0, int a1, int s) {
+        const int nqf1 = sPf[lf] + 2;
+        return sLf[lf][a0 * nqf1 + (s % nqf1)] * sLf[lf][a1 * nqf1 + (s / nqf1)];
+    };
+    auto mu_face = [&](int lf, int b, int s) {
+        const int pf1 = sPf[lf] + 1, nqf1 = sPf[lf] + 2;
+        return sMf[lf][(b % pf1) * nqf1 + (s % nqf1)] * sMf[lf][(b / pf1) * nqf1 + (s / nqf1)];
+    };
+
+    if (rb < 20) {
+        // ================= interior rows of field rb
+        const int r = rb;
+        const bool qrow = r < 15;
+        const int c = qrow ? r / 3 : r - 15, j = qrow ? r % 3 : 0;
+        double *Er = E + (int64_t)r * Np * ld;
+        // register tile: thread (ti, tk) owns rows ti + 16a, cols tk + 16b (T = ceil(max N_p / 16))
+        const int ti = tid / 16, tk = tid % 16;
+        for (int sblk = 0; sblk < 20; ++sblk) {
+            __syncthreads();  // previous block's readers of sFc are done
+            bool nonzero = qrow ? (sblk == r || sblk == 15 + c) : true;
+            if (!nonzero) {
+                for (int t = tid; t < Np * Np; t += blockDim.x) Er[(int64_t)(t / Np) * ld + sblk * Np + t % Np] = 0.0;
+                continue;
+            }
+            // face coefficients of this block (conservation rows only)
+            if (!qrow) {
+                const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
+                for (int t = tid; t < 6 * 36; t += blockDim.x) {
+                    const int lf = t / 36, s = t % 36;
+                    sFc[t] = (s < sNqf[lf]) ? P.dt * qpe[sFbase[lf] + (int64_t)(25 * c + slot) * sNqf[lf] + s] : 0.0;
+                }
+            }
+            double acc[T][T];
+#pragma unroll
+            for (int a = 0; a < T; ++a)
+#pragma unroll
+                for (int b = 0; b < T; ++b) acc[a][b] = 0.0;
+            for (int g0 = 0; g0 < Nq; g0 += kCh) {
+                const int gn = min(kCh, Nq - g0);
+                __syncthreads();
+                for (int t = tid; t < 128 * kCh; t += blockDim.x) {
+                    const int i = t / kCh, gg = t % kCh, g = g0 + gg;
+                    double h = 0.0, ph = 0.0;
+                    if (i < Np && gg < gn) {
+                        double v[4];
+                        R.phi_all(i, g, v);
+                        ph = v[0];
+                        if (qrow) {
+                            if (sblk == r) h = vg[g] * v[0];
+                            else h = vg[g] * (vg[(1 + j) * Nq + g] * v[1] + vg[(4 + j) * Nq + g] * v[2] + vg[(7 + j) * Nq + g] * v[3]);
+                        } else {
+                            const double *cf = qpe + (int64_t)(4 * (20 * c + sblk)) * Nq + g;
+                            h = cf[0] * v[0] + cf[Nq] * v[1] + cf[2 * Nq] * v[2] + cf[3 * Nq] * v[3];
+                        }
+                    }
+                    sH[t] = h;
+                    sP[t] = ph;
+                }
+                __syncthreads();
+                for (int gg = 0; gg < gn; ++gg) {
+                    double hv[T], pv[T];
+#pragma unroll
+                    for (int a = 0; a < T; ++a) hv[a] = sH[(ti + 16 * a) * kCh + gg];
+#pragma unroll
+                    for (int b = 0; b < T; ++b) pv[b] = sP[(tk + 16 * b) * kCh + gg];
+#pragma unroll
+                    for (int a = 0; a < T; ++a)
+#pragma unroll
+                        for (int b = 0; b < T; ++b) acc[a][b] += hv[a] * pv[b];
+                }
+            }
+            __syncthreads();  // sFc ready (written before the chunk loop's first barrier)
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                const int i = ti + 16 * a;
+                if (i >= Np) continue;
+#pragma unroll
+                for (int b = 0; b < T; ++b) {
+                    const int k = tk + 16 * b;
+                    if (k >= Np) continue;
+                    double v = acc[a][b];
+                    if (!qrow) {
+                        for (int lf = 0; lf < 6; ++lf) {
+                            int ia0, ia1, ka0, ka1;
+                            if (!on_face(i, p1, lf, ia0, ia1) || !on_face(k, p1, lf, ka0, ka1)) continue;
+                            for (int s = 0; s < sNqf[lf]; ++s)
+                                v += sFc[lf * 36 + s] * phi_face(lf, ia0, ia1, s) * phi_face(lf, ka0, ka1, s);
+                        }
+                    }
+                    Er[(int64_t)i * ld + sblk * Np + k] = v;
+                }
+            }
+        }
+        // ---- B columns: face lf, component cp, trace node b
+        __syncthreads();
+        for (int t = tid; t < 6 * 5 * 36; t += blockDim.x) {
+            const int lf = t / 180, cp = (t / 36) % 5, s = t % 36;
+            double v = 0.0;
+            if (s < sNqf[lf]) {
+                if (qrow) v = (cp == c) ? -dm.fgeo[dm.fgeo_off[6 * e + lf] + (int64_t)j * sNqf[lf] + s] : 0.0;
+                else v = P.dt * qpe[sFbase[lf] + (int64_t)(25 * c + 20 + cp) * sNqf[lf] + s];
+            }
+            sFB[t] = v;
+        }
+        __syncthreads();
+        for (int t = tid; t < Np * f; t += blockDim.x) {
+            const int i = t / f, col = t % f;
+            int lf = 0;
+            while (col >= toff[lf + 1]) ++lf;
+            const int pf1 = sPf[lf] + 1, Nfp = pf1 * pf1;
+            const int cp = (col - toff[lf]) / Nfp, b = (col - toff[lf]) % Nfp;
+            double v = 0.0;
+            int a0, a1;
+            if (on_face(i, p1, lf, a0, a1) && (!qrow || cp == c)) {
+                const double *cf = sFB + (lf * 5 + cp) * 36;
+                for (int s = 0; s < sNqf[lf]; ++s) v += cf[s] * phi_face(lf, a0, a1, s) * mu_face(lf, b, s);
+            }
+            Er[(int64_t)i * ld + n + col] = v;
+        }
+        // ---- residual column and padding
+        for (int i = tid; i < Np; i += blockDim.x) {
+            double v = 0.0;
+            const double *rc = qpe + (int64_t)kVJac * Nq + (int64_t)(4 * r) * Nq;
+            for (int g = 0; g < Nq; ++g) {
+                double ph[4];
+                R.phi_all(i, g, ph);
+                v += rc[g] * ph[0] + rc[Nq + g] * ph[1] + rc[2 * Nq + g] * ph[2] + rc[3 * Nq + g] * ph[3];
+            }
+            for (int lf = 0; lf < 6; ++lf) {
+                int a0, a1;
+                if (!on_face(i, p1, lf, a0, a1)) continue;
+                const int Nqf = sNqf[lf];
+                const double *fb = qpe + sFbase[lf];
+                const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
+                for (int s = 0; s < Nqf; ++s) {
+                    const double ph = phi_face(lf, a0, a1, s);
+                    if (qrow) v -= fgl[j * Nqf + s] * fb[(135 + c) * Nqf + s] * ph;
+                    else v += P.dt * fb[(125 + c) * Nqf + s] * ph;
+                }
+            }
+            Er[(int64_t)i * ld + n + f] = v;
+            for (int64_t col = n + f + 1; col < ld; ++col) Er[(int64_t)i * ld + col] = 0.0;
+        }
+    } else {
+        // ================= trace rows of local face lf
+        const int lf = rb - 20;
+        const int pf1 = sPf[lf] + 1, Nfp = pf1 * pf1, Nqf = sNqf[lf];
+        const int F = dm.elem_face[6 * e + lf], bc = dm.face_bc[F];
+        const double *fb = qpe + sFbase[lf];
+        const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
+        double *Et = E + (int64_t)(n + toff[lf]) * ld;
+        const int nrow = 5 * Nfp;
+        for (int t = tid; t < nrow * (int)ld; t += blockDim.x) {
+            const int row = t / (int)ld, col = t % (int)ld;
+            const int c = row / Nfp, a = row % Nfp;
+            double v = 0.0;
+            if (col < n) {
+                const int sblk = col / Np, k = col % Np;
+                int ka0, ka1;
+                if (!bc && on_face(k, p1, lf, ka0, ka1)) {
+                    const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
+                    const double *cf = fb + (int64_t)(25 * c + slot) * Nqf;
+                    for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * phi_face(lf, ka0, ka1, s);
+                }
+            } else if (col < n + f) {
+                const int cc = col - n;
+                if (cc >= toff[lf] && cc < toff[lf + 1]) {
+                    const int cp = (cc - toff[lf]) / Nfp, b = (cc - toff[lf]) % Nfp;
+                    if (bc) {
+                        if (cp == c)
+                            for (int s = 0; s < Nqf; ++s) v += fgl[3 * Nqf + s] * mu_face(lf, a, s) * mu_face(lf, b, s);
+                    } else {
+                        const double *cf = fb + (int64_t)(25 * c + 20 + cp) * Nqf;
+                        for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * mu_face(lf, b, s);
+                    }
+                }
+            } else if (col == n + f) {
+                const double *cf = fb + (int64_t)((bc ? 130 : 125) + c) * Nqf;
+                for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s);
+            }
+            Et[(int64_t)row * ld + col] = v;
+        }
+    }
+}
+
+}  // namespace
+
+int launch_element_system(const hdg_ctx *ctx, int e0, int ne, const double *Q, const double *U,
+                          const double *Un, const double *Uhat, const double *nu, const double *Ub,
+                          double *E, double *qp, hipStream_t s) {
+    const DevMesh &dm = ctx->dm;
+    const Phys P = ctx->phys;
+    hipLaunchKernelGGL(k_qp_volume, dim3(ne), dim3(256), 0, s, dm, P, e0, Q, U, Un, nu, qp);
+    hipLaunchKernelGGL(k_qp_face, dim3(6, ne), dim3(64), 0, s, dm, P, e0, Q, U, Uhat, nu, Ub, qp);
+    int maxp = 1;
+    for (int e = e0; e < e0 + ne; ++e) maxp = std::max(maxp, ctx->elem_p[e]);
+    const double *qpc = qp;
+    switch (maxp) {
+        case 1: hipLaunchKernelGGL(k_assemble_rows<1>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+        case 2: hipLaunchKernelGGL(k_assemble_rows<2>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+        case 3: hipLaunchKernelGGL(k_assemble_rows<4>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+        default: hipLaunchKernelGGL(k_assemble_rows<8>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace hdg

@@ -1,0 +1,526 @@
+// Trace-space kernels: assembly of the condensed system (eq. schur-trace),
+// the block-sparse matvec, the one-level additive Schwarz preconditioner
+// (eq. additive-schwarz), left-preconditioned GMRES, and the interior
+// recovery (eq. local-elimination).  Every sum over element contributions is
+// a gather in a fixed order: results are bit-reproducible, no atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "hdg_internal.h"
+
+namespace hdg {
+namespace {
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__device__ inline double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
+
+// ------------------------------------------------------------------ assembly
+__global__ void __launch_bounds__(256) k_assemble_blocks(DevMesh dm, const double *__restrict__ SK,
+                                                         double *__restrict__ S) {
+    const int k = blockIdx.x;
+    const int c0 = dm.blk_src_ptr[k], c1 = dm.blk_src_ptr[k + 1];
+    const int e_first = dm.blk_src[3 * c0], a_first = dm.blk_src[3 * c0 + 1], b_first = dm.blk_src[3 * c0 + 2];
+    const int *tf = dm.toff + 7 * e_first;
+    const int bF = tf[a_first + 1] - tf[a_first], bG = tf[b_first + 1] - tf[b_first];
+    double *out = S + dm.bsr_val_off[k];
+    for (int t = threadIdx.x; t < bF * bG; t += blockDim.x) {
+        const int ii = t % bF, jj = t / bF;
+        double v = 0.0;
+        for (int c = c0; c < c1; ++c) {
+            const int e = dm.blk_src[3 * c], a = dm.blk_src[3 * c + 1], b = dm.blk_src[3 * c + 2];
+            const int *to = dm.toff + 7 * e;
+            const int fe = to[6];
+            v += SK[dm.SK_off[e] + (int64_t)(to[b] + jj) * fe + to[a] + ii];
+        }
+        out[t] = v;
+    }
+}
+
+__global__ void __launch_bounds__(128) k_assemble_g(DevMesh dm, const double *__restrict__ SK, double *__restrict__ g) {
+    const int F = blockIdx.x;
+    const int bF = (int)(dm.face_off[F + 1] - dm.face_off[F]);
+    const int s0 = dm.face_src_ptr[F], s1 = dm.face_src_ptr[F + 1];
+    for (int i = threadIdx.x; i < bF; i += blockDim.x) {
+        double v = 0.0;
+        for (int s = s0; s < s1; ++s) {
+            const int e = dm.face_src[2 * s], a = dm.face_src[2 * s + 1];
+            const int *to = dm.toff + 7 * e;
+            const int fe = to[6];
+            v += SK[dm.SK_off[e] + (int64_t)fe * fe + to[a] + i];
+        }
+        g[dm.face_off[F] + i] = v;
+    }
+}
+
+// -------------------------------------------------------------------- matvec
+constexpr int kMaxRowBlocks = 16;
+
+__global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__restrict__ S,
+                                                const double *__restrict__ x, double *__restrict__ y) {
+    const int F = blockIdx.x;
+    const int bF = (int)(dm.face_off[F + 1] - dm.face_off[F]);
+    const int k0 = dm.bsr_row_ptr[F], nk = dm.bsr_row_ptr[F + 1] - k0;
+    __shared__ double sx[kMaxRowBlocks * 125];
+    __shared__ int sxo[kMaxRowBlocks + 1];
+    __shared__ double sred[256];
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int q = 0; q < nk; ++q) {
+            sxo[q] = o;
+            const int G = dm.bsr_col[k0 + q];
+            o += (int)(dm.face_off[G + 1] - dm.face_off[G]);
+        }
+        sxo[nk] = o;
+    }
+    __syncthreads();
+    for (int q = 0; q < nk; ++q) {
+        const int G = dm.bsr_col[k0 + q];
+        const int bG = sxo[q + 1] - sxo[q];
+        for (int t = threadIdx.x; t < bG; t += blockDim.x) sx[sxo[q] + t] = x[dm.face_off[G] + t];
+    }
+    __syncthreads();
+    const int W = 256 / bF;
+    const int i = threadIdx.x % bF, w = threadIdx.x / bF;
+    double acc = 0.0;
+    if (w < W) {
+        for (int q = 0; q < nk; ++q) {
+            const double *blk = S + dm.bsr_val_off[k0 + q];
+            const double *xs = sx + sxo[q];
+            const int bG = sxo[q + 1] - sxo[q];
+            int j = w;
+            for (; j + 3 * W < bG; j += 4 * W) {
+                const double a0 = ld_stream(blk + i + (int64_t)j * bF);
+                const double a1 = ld_stream(blk + i + (int64_t)(j + W) * bF);
+                const double a2 = ld_stream(blk + i + (int64_t)(j + 2 * W) * bF);
+                const double a3 = ld_stream(blk + i + (int64_t)(j + 3 * W) * bF);
+                acc += a0 * xs[j];
+                acc += a1 * xs[j + W];
+                acc += a2 * xs[j + 2 * W];
+                acc += a3 * xs[j + 3 * W];
+            }
+            for (; j < bG; j += W) acc += ld_stream(blk + i + (int64_t)j * bF) * xs[j];
+        }
+    }
+    sred[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < bF) {
+        double v = 0.0;
+        for (int ww = 0; ww < W; ++ww) v += sred[ww * bF + threadIdx.x];
+        y[dm.face_off[F] + threadIdx.x] = v;
+    }
+}
+
+// ------------------------------------------------------------- Schwarz setup
+// Systems [[S_r, I], [I, 0]] (row-major, row stride e_ld(f, f)).
+__global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__restrict__ S, double *__restrict__ sys) {
+    const int e = blockIdx.y;
+    const int *to = dm.toff + 7 * e;
+    const int f = to[6];
+    const int64_t ld = e_ld(f, f);
+    double *base = sys + dm.asmsys_off[e];
+    const int64_t total = (int64_t)2 * f * ld;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(t / ld), c = (int)(t % ld);
+        double v = 0.0;
+        if (r < f) {
+            if (c < f) {
+                int a = 0, b = 0;
+                while (r >= to[a + 1]) ++a;
+                while (c >= to[b + 1]) ++b;
+                const int k = dm.asm_blk[36 * e + 6 * a + b];
+                const int bF = to[a + 1] - to[a];
+                v = S[dm.bsr_val_off[k] + (r - to[a]) + (int64_t)(c - to[b]) * bF];
+            } else if (c < 2 * f) {
+                v = (c - f == r) ? 1.0 : 0.0;
+            }
+        } else if (c < f) {
+            v = (c == r - f) ? 1.0 : 0.0;
+        }
+        base[t] = v;
+    }
+}
+
+// Sinv (column-major f x f) = -(trailing block), FP64 or FP32
+template <typename T>
+__global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const double *__restrict__ sys, T *__restrict__ Sinv) {
+    const int e = blockIdx.z;
+    const int f = dm.toff[7 * e + 6];
+    const int64_t ld = e_ld(f, f);
+    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    if (i0 >= f || j0 >= f) return;
+    const double *base = sys + dm.asmsys_off[e];
+    T *out = Sinv + dm.asm_off[e];
+    __shared__ double tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = i0 + r, j = j0 + tx;
+        tile[r][tx] = (i < f && j < f) ? -base[(int64_t)(f + i) * ld + f + j] : 0.0;
+    }
+    __syncthreads();
+    for (int c = ty; c < 32; c += 8) {
+        const int j = j0 + c, i = i0 + tx;
+        if (i < f && j < f) out[(int64_t)j * f + i] = (T)tile[tx][c];
+    }
+}
+
+// ------------------------------------------------------------- Schwarz apply
+template <typename T>
+__global__ void __launch_bounds__(256) k_asm_local(DevMesh dm, const T *__restrict__ Sinv, const double *__restrict__ r,
+                                                   double *__restrict__ zloc) {
+    const int e = blockIdx.x;
+    const int *to = dm.toff + 7 * e;
+    const int f = to[6];
+    __shared__ double sy[750];
+    for (int lf = 0; lf < 6; ++lf) {
+        const int F = dm.elem_face[6 * e + lf];
+        const int len = to[lf + 1] - to[lf];
+        for (int t = threadIdx.x; t < len; t += blockDim.x) sy[to[lf] + t] = r[dm.face_off[F] + t];
+    }
+    __syncthreads();
+    const T *M = Sinv + dm.asm_off[e];
+    for (int i = threadIdx.x; i < f; i += blockDim.x) {
+        double acc = 0.0;
+        int j = 0;
+        for (; j + 3 < f; j += 4) {
+            const double a0 = (double)M[(int64_t)j * f + i], a1 = (double)M[(int64_t)(j + 1) * f + i];
+            const double a2 = (double)M[(int64_t)(j + 2) * f + i], a3 = (double)M[(int64_t)(j + 3) * f + i];
+            acc += a0 * sy[j];
+            acc += a1 * sy[j + 1];
+            acc += a2 * sy[j + 2];
+            acc += a3 * sy[j + 3];
+        }
+        for (; j < f; ++j) acc += (double)M[(int64_t)j * f + i] * sy[j];
+        zloc[dm.tloc_off[e] + i] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(128) k_asm_gather(DevMesh dm, const double *__restrict__ zloc, double *__restrict__ z) {
+    const int F = blockIdx.x;
+    const int bF = (int)(dm.face_off[F + 1] - dm.face_off[F]);
+    const int s0 = dm.face_src_ptr[F], s1 = dm.face_src_ptr[F + 1];
+    for (int i = threadIdx.x; i < bF; i += blockDim.x) {
+        double v = 0.0;
+        for (int s = s0; s < s1; ++s) {
+            const int e = dm.face_src[2 * s], a = dm.face_src[2 * s + 1];
+            v += zloc[dm.tloc_off[e] + dm.toff[7 * e + a] + i];
+        }
+        z[dm.face_off[F] + i] = v;
+    }
+}
+
+// --------------------------------------------------------------------- GMRES
+constexpr int kDotBlocks = 256;
+
+// partial[b * stride + v] = sum over block b's slice of V[v] . w   (v < nv)
+__global__ void __launch_bounds__(256) k_dot_partial(const double *__restrict__ V, int nv, int64_t ldv,
+                                                     const double *__restrict__ w, int64_t N,
+                                                     double *__restrict__ partial, int stride) {
+    __shared__ double red[256];
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * chunk, i1 = min(N, i0 + chunk);
+    for (int v = 0; v < nv; ++v) {
+        const double *Vv = V + v * ldv;
+        double s = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) s += Vv[i] * w[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blockIdx.x * stride + v] = red[0];
+        __syncthreads();
+    }
+}
+
+// out[v] = (accumulate ? out[v] : 0) + sum_b partial[b * stride + v]
+__global__ void k_dot_final(const double *__restrict__ partial, int nblk, int stride, int nv, double *__restrict__ out,
+                            int accumulate) {
+    const int v = threadIdx.x + blockIdx.x * blockDim.x;
+    if (v >= nv) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[b * stride + v];
+    out[v] = accumulate ? out[v] + s : s;
+}
+
+// w -= sum_v coef[v] V[v]
+__global__ void __launch_bounds__(256) k_sub_multi(const double *__restrict__ V, int nv, int64_t ldv,
+                                                   const double *__restrict__ coef, double *__restrict__ w, int64_t N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = w[i];
+        for (int v = 0; v < nv; ++v) s -= coef[v] * V[v * ldv + i];
+        w[i] = s;
+    }
+}
+
+// dst = src / *nrm  (0 if the norm is 0)
+__global__ void __launch_bounds__(256) k_scale_inv(const double *__restrict__ src, const double *__restrict__ nrm_sq,
+                                                   double *__restrict__ dst, int64_t N) {
+    const double nr = sqrt(*nrm_sq);
+    const double s = (nr > 0.0) ? 1.0 / nr : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] * s;
+}
+
+// Start of the cycle: gam[0] = beta = ||r0||, hist[0] = beta.
+__global__ void k_gmres_start(const double *__restrict__ nrm_sq, double *__restrict__ gam, double *__restrict__ hist, int m) {
+    const double b = sqrt(*nrm_sq);
+    for (int i = 0; i <= m; ++i) gam[i] = 0.0;
+    gam[0] = b;
+    hist[0] = b;
+}
+
+// Column j of H (length j+2, column-major ld m+1): fold in the norm, apply
+// the previous rotations, form the new one, update gam and the history.
+__global__ void k_givens(double *__restrict__ H, int m, int j, const double *__restrict__ nrm_sq,
+                         double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ gam,
+                         double *__restrict__ hist) {
+    double *h = H + (int64_t)j * (m + 1);
+    h[j + 1] = sqrt(*nrm_sq);
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+    }
+    const double a = h[j], b = h[j + 1];
+    const double den = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (den > 0.0) { c = a / den; s = b / den; }
+    cs[j] = c;
+    sn[j] = s;
+    h[j] = den;
+    h[j + 1] = 0.0;
+    gam[j + 1] = -s * gam[j];
+    gam[j] = c * gam[j];
+    hist[j + 1] = fabs(gam[j + 1]);
+}
+
+// y = R^{-1} gam (upper triangular m x m part of H); skips zero pivots
+__global__ void k_upper_solve(const double *__restrict__ H, int m, const double *__restrict__ gam, double *__restrict__ y) {
+    for (int i = m - 1; i >= 0; --i) {
+        double s = gam[i];
+        for (int k = i + 1; k < m; ++k) s -= H[(int64_t)k * (m + 1) + i] * y[k];
+        const double d = H[(int64_t)i * (m + 1) + i];
+        y[i] = (d != 0.0) ? s / d : 0.0;
+    }
+}
+
+// x = sum_v y[v] V[v]
+__global__ void __launch_bounds__(256) k_combine(const double *__restrict__ V, int nv, int64_t ldv,
+                                                 const double *__restrict__ y, double *__restrict__ x, int64_t N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int v = 0; v < nv; ++v) s += y[v] * V[v * ldv + i];
+        x[i] = s;
+    }
+}
+
+// ------------------------------------------------------------------ recovery
+// y_i = E[i][n+f] + sum_j E[i][n+j] dUh^K_j for i < n   (one wave per row),
+// then (FP64) back substitution with the upper triangle of E's first n
+// columns; dQU = -x.
+constexpr int kRB = 64;
+
+__global__ void __launch_bounds__(256) k_recover(DevMesh dm, int e0, int backsub, const double *__restrict__ Ebase,
+                                                 const double *__restrict__ dUhat, double *__restrict__ dQU) {
+    const int e = e0 + blockIdx.x;
+    const int p = dm.elem_p[e], Np = (p + 1) * (p + 1) * (p + 1), n = 20 * Np;
+    const int *to = dm.toff + 7 * e;
+    const int f = to[6];
+    const int64_t ld = e_ld(n, f);
+    const double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    __shared__ double sd[750];
+    __shared__ double sy[2500];
+    __shared__ double sU[kRB][kRB + 1];
+    for (int lf = 0; lf < 6; ++lf) {
+        const int F = dm.elem_face[6 * e + lf];
+        const int len = to[lf + 1] - to[lf];
+        for (int t = threadIdx.x; t < len; t += blockDim.x) sd[to[lf] + t] = dUhat[dm.face_off[F] + t];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = wave; i < n; i += 4) {
+        const double *row = E + (int64_t)i * ld + n;
+        double s = 0.0;
+        for (int j = lane; j < f; j += 64) s += row[j] * sd[j];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) sy[i] = s + row[f];
+    }
+    __syncthreads();
+    if (backsub) {
+        for (int i1 = n; i1 > 0; i1 -= kRB) {
+            const int i0 = max(0, i1 - kRB), nb = i1 - i0;
+            for (int t = threadIdx.x; t < kRB * kRB; t += blockDim.x) {
+                const int r = t / kRB, c = t % kRB;
+                sU[r][c] = (r < nb && c < nb) ? E[(int64_t)(i0 + r) * ld + i0 + c] : 0.0;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                // diagonal block: lanes hold rows i0 + lane
+                double yl = (lane < nb) ? sy[i0 + lane] : 0.0;
+                for (int c = nb - 1; c >= 0; --c) {
+                    const double xc = __shfl(yl, c) / sU[c][c];
+                    if (lane == c) yl = xc;
+                    else if (lane < c) yl -= sU[lane][c] * xc;
+                }
+                if (lane < nb) sy[i0 + lane] = yl;
+            }
+            __syncthreads();
+            // rows above: y[r] -= U[r][i0:i1] x[i0:i1]
+            for (int r = threadIdx.x; r < i0; r += blockDim.x) {
+                const double *row = E + (int64_t)r * ld + i0;
+                double s = sy[r];
+                for (int c = 0; c < nb; ++c) s -= row[c] * sy[i0 + c];
+                sy[r] = s;
+            }
+            __syncthreads();
+        }
+    }
+    double *out = dQU + 20 * dm.node_off[e];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = -sy[i];
+}
+
+inline int grid_for(int64_t n, int threads = 256, int cap = 2048) {
+    int64_t g = (n + threads - 1) / threads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+}  // namespace
+
+int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, hipStream_t s) {
+    const DevMesh &dm = ctx->dm;
+    const int nnzb = (int)ctx->bsr_col.size();
+    hipLaunchKernelGGL(k_assemble_blocks, dim3(nnzb), dim3(256), 0, s, dm, SK, S);
+    hipLaunchKernelGGL(k_assemble_g, dim3(ctx->n_face), dim3(128), 0, s, dm, SK, g);
+    return (int)hipGetLastError();
+}
+
+int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_matvec, dim3(ctx->n_face), dim3(256), 0, s, ctx->dm, S, x, y);
+    return (int)hipGetLastError();
+}
+
+size_t asm_setup_work_bytes(const hdg_ctx *ctx) {
+    size_t sys = sizeof(double) * (size_t)ctx->asmsys_off[ctx->n_elem];
+    size_t iw = bordered_lu_work(ctx, ctx->n_elem);
+    return (sys + 255) / 256 * 256 + (iw + 255) / 256 * 256;
+}
+
+int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info, void *work,
+                     hipStream_t s) {
+    const DevMesh &dm = ctx->dm;
+    double *sys = (double *)work;
+    size_t sys_bytes = (sizeof(double) * (size_t)ctx->asmsys_off[ctx->n_elem] + 255) / 256 * 256;
+    void *iwork = (void *)((char *)work + sys_bytes);
+    hipLaunchKernelGGL(k_asm_build, dim3(64, ctx->n_elem), dim3(256), 0, s, dm, S, sys);
+    int err = run_asm_inversion(ctx, sys, info, iwork, s);
+    if (err) return err;
+    const int maxf = ctx->max_f;
+    dim3 grid((maxf + 31) / 32, (maxf + 31) / 32, ctx->n_elem);
+    if (prec == HDG_FP64)
+        hipLaunchKernelGGL(k_asm_extract<double>, grid, dim3(256), 0, s, dm, (const double *)sys, (double *)Sinv);
+    else
+        hipLaunchKernelGGL(k_asm_extract<float>, grid, dim3(256), 0, s, dm, (const double *)sys, (float *)Sinv);
+    return (int)hipGetLastError();
+}
+
+size_t asm_apply_work_bytes(const hdg_ctx *ctx) {
+    return (sizeof(double) * (size_t)ctx->tloc_off[ctx->n_elem] + 255) / 256 * 256;
+}
+
+int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z, void *work,
+                     hipStream_t s) {
+    const DevMesh &dm = ctx->dm;
+    double *zloc = (double *)work;
+    if (prec == HDG_FP64)
+        hipLaunchKernelGGL(k_asm_local<double>, dim3(ctx->n_elem), dim3(256), 0, s, dm, (const double *)Sinv, r, zloc);
+    else
+        hipLaunchKernelGGL(k_asm_local<float>, dim3(ctx->n_elem), dim3(256), 0, s, dm, (const float *)Sinv, r, zloc);
+    hipLaunchKernelGGL(k_asm_gather, dim3(ctx->n_face), dim3(128), 0, s, dm, (const double *)zloc, z);
+    return (int)hipGetLastError();
+}
+
+// GMRES workspace (doubles): V[(m+1) N] | w[N] | t[N] | zloc | H[(m+1) m] | cs[m] | sn[m] | gam[m+1] |
+//                            hcol[m+1] | y[m] | partial[kDotBlocks (m+2)] | scal[8]
+static size_t gmres_layout(const hdg_ctx *ctx, int m, size_t *off) {
+    const size_t N = (size_t)ctx->face_off[ctx->n_face];
+    const size_t nz = (size_t)ctx->tloc_off[ctx->n_elem];
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t at = o; o += (n + 31) / 32 * 32; return at; };
+    off[0] = take((m + 1) * N);
+    off[1] = take(N);
+    off[2] = take(N);
+    off[3] = take(nz);
+    off[4] = take((size_t)(m + 1) * m);
+    off[5] = take(m);
+    off[6] = take(m);
+    off[7] = take(m + 1);
+    off[8] = take(m + 1);
+    off[9] = take(m);
+    off[10] = take((size_t)kDotBlocks * (m + 2));
+    off[11] = take(8);
+    return o * sizeof(double);
+}
+
+size_t gmres_work_bytes(const hdg_ctx *ctx, int m) {
+    size_t off[12];
+    return gmres_layout(ctx, m, off);
+}
+
+int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv, const double *g, int m, double *x,
+                 double *hist, void *work, hipStream_t s) {
+    size_t off[12];
+    gmres_layout(ctx, m, off);
+    double *W = (double *)work;
+    double *V = W + off[0], *w = W + off[1], *t = W + off[2], *zloc = W + off[3], *H = W + off[4];
+    double *cs = W + off[5], *sn = W + off[6], *gam = W + off[7], *hcol = W + off[8], *y = W + off[9];
+    double *partial = W + off[10], *scal = W + off[11];
+    const int64_t N = ctx->face_off[ctx->n_face];
+    const int stride = m + 2;
+    const int gN = grid_for(N);
+    int err;
+    // r0 = M^{-1} g, beta = ||r0||, v0 = r0 / beta
+    if ((err = launch_asm_apply(ctx, prec, Sinv, g, w, zloc, s))) return err;
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)w, 1, (int64_t)0,
+                       (const double *)w, N, partial, stride);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, (const double *)partial, kDotBlocks, stride, 1, scal, 0);
+    hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, s, (const double *)scal, gam, hist, m);
+    hipLaunchKernelGGL(k_scale_inv, dim3(gN), dim3(256), 0, s, (const double *)w, (const double *)scal, V, N);
+    for (int j = 0; j < m; ++j) {
+        double *vj = V + (int64_t)j * N;
+        if ((err = launch_matvec(ctx, S, vj, t, s))) return err;
+        if ((err = launch_asm_apply(ctx, prec, Sinv, t, w, zloc, s))) return err;
+        double *hj = H + (int64_t)j * (m + 1);
+        // classical Gram-Schmidt, applied twice
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)V, j + 1, N,
+                               (const double *)w, N, partial, stride);
+            hipLaunchKernelGGL(k_dot_final, dim3((j + 1 + 63) / 64), dim3(64), 0, s, (const double *)partial,
+                               kDotBlocks, stride, j + 1, pass == 0 ? hj : hcol, 0);
+            hipLaunchKernelGGL(k_sub_multi, dim3(gN), dim3(256), 0, s, (const double *)V, j + 1, N,
+                               (const double *)(pass == 0 ? hj : hcol), w, N);
+            if (pass == 1)
+                hipLaunchKernelGGL(k_dot_final, dim3((j + 1 + 63) / 64), dim3(64), 0, s, (const double *)partial,
+                                   kDotBlocks, stride, j + 1, hj, 1);
+        }
+        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)w, 1, (int64_t)0,
+                           (const double *)w, N, partial, stride);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, (const double *)partial, kDotBlocks, stride, 1, scal, 0);
+        hipLaunchKernelGGL(k_scale_inv, dim3(gN), dim3(256), 0, s, (const double *)w, (const double *)scal,
+                           V + (int64_t)(j + 1) * N, N);
+        hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, H, m, j, (const double *)scal, cs, sn, gam, hist);
+    }
+    hipLaunchKernelGGL(k_upper_solve, dim3(1), dim3(1), 0, s, (const double *)H, m, (const double *)gam, y);
+    hipLaunchKernelGGL(k_combine, dim3(gN), dim3(256), 0, s, (const double *)V, m, N, (const double *)y, x, N);
+    return (int)hipGetLastError();
+}
+
+int launch_recover(const hdg_ctx *ctx, int prec, int e0, int ne, const double *E, const double *dUhat, double *dQU,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_recover, dim3(ne), dim3(256), 0, s, ctx->dm, e0, prec == HDG_FP64 ? 1 : 0, E, dUhat, dQU);
+    return (int)hipGetLastError();
+}
+
+}  // namespace hdg

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of libhdg (argument marshalling only).
+
+Every entry point of ``include/hdg.h`` has a method of the same name on
+:class:`Context`.  Arrays are torch tensors on the GPU (device memory) and the
+stream is torch's current stream; all arithmetic happens in the HIP kernels of
+libhdg.  There is no fallback: if the library is missing or the device is not
+a GPU, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+HDG_FP64 = 0
+HDG_MIXED = 1
+
+LAYOUT = {"node_off": 0, "face_off": 1, "E_off": 2, "SK_off": 3, "bsr_row_ptr": 4, "bsr_col": 5,
+          "bsr_val_off": 6, "asm_off": 7, "elem_n": 8, "elem_f": 9}
+
+EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_layout_length",
+           "hdg_workspace_size", "hdg_local_residual_jacobian", "hdg_condense", "hdg_assemble_trace",
+           "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior"]
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_lib = None
+
+
+class HDGError(RuntimeError):
+    pass
+
+
+class _MeshDesc(ctypes.Structure):
+    _fields_ = [("n_elem", _i), ("n_face", _i), ("n_vert", _i), ("vert_xyz", _vp), ("elem_vert", _vp),
+                ("elem_face", _vp), ("face_elem", _vp), ("face_bc", _vp), ("elem_p", _vp)]
+
+
+class _Phys(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("reynolds", ctypes.c_double),
+                ("mach", ctypes.c_double), ("tau", ctypes.c_double), ("dt", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("visc_law", _i)]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhdg.so (no GPU needed to load it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HDGError(f"libhdg not built: {path} is missing (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    L.hdg_create.argtypes = [ctypes.POINTER(_MeshDesc), ctypes.POINTER(_Phys), ctypes.POINTER(_vp)]
+    L.hdg_destroy.argtypes = [_vp]
+    L.hdg_destroy.restype = None
+    L.hdg_status_string.argtypes = [_i]
+    L.hdg_status_string.restype = ctypes.c_char_p
+    L.hdg_layout.argtypes = [_vp, _i, _vp, ctypes.c_int64]
+    L.hdg_layout_length.argtypes = [_vp, _i]
+    L.hdg_layout_length.restype = ctypes.c_int64
+    L.hdg_workspace_size.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]
+    L.hdg_local_residual_jacobian.argtypes = [_vp, _i, _i] + [_vp] * 7 + [_vp, ctypes.c_size_t, _vp]
+    L.hdg_condense.argtypes = [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_assemble_trace.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.hdg_face_matvec.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.hdg_asm_setup.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_asm_block_apply.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_gmres.argtypes = [_vp, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_recover_interior.argtypes = [_vp, _i, _i, _i, _vp, _vp, _vp, _vp]
+    for name in EXPORTS:
+        if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length"):
+            getattr(L, name).restype = _i
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = _lib.hdg_status_string(rc).decode()
+        raise HDGError(f"{what} failed: {msg} ({rc})")
+
+
+def _ptr(t, dtype=None, numel=None, name="array"):
+    """Device pointer of a contiguous GPU tensor, checking dtype and size."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise HDGError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise HDGError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise HDGError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise HDGError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """An hdg_ctx for one mesh and one set of physical constants."""
+
+    def __init__(self, mesh, wl_or_phys):
+        import torch
+        if not torch.cuda.is_available():
+            raise HDGError("libhdg needs a GPU (torch.cuda.is_available() is False)")
+        L = load_library()
+        self.mesh = mesh
+        self._keep = dict(
+            vert=np.ascontiguousarray(mesh.vert_xyz, dtype=np.float64),
+            ev=np.ascontiguousarray(mesh.elem_vert, dtype=np.int32),
+            ef=np.ascontiguousarray(mesh.elem_face, dtype=np.int32),
+            fe=np.ascontiguousarray(mesh.face_elem, dtype=np.int32),
+            bc=np.ascontiguousarray(mesh.face_bc, dtype=np.int8),
+            p=np.ascontiguousarray(mesh.elem_p, dtype=np.int8))
+        k = self._keep
+        desc = _MeshDesc(mesh.n_elem, mesh.n_face, mesh.n_vert, k["vert"].ctypes.data, k["ev"].ctypes.data,
+                         k["ef"].ctypes.data, k["fe"].ctypes.data, k["bc"].ctypes.data, k["p"].ctypes.data)
+        w = wl_or_phys
+        phys = _Phys(w.gamma, w.prandtl, w.reynolds, w.mach, w.tau, w.dt, w.alpha, int(w.visc_law))
+        torch.cuda.init()
+        h = _vp()
+        _check(L.hdg_create(ctypes.byref(desc), ctypes.byref(phys), ctypes.byref(h)), "hdg_create")
+        self.h = h
+        self.L = L
+        self.layout = {name: self._layout(kind) for name, kind in LAYOUT.items()}
+        self.n_elem = mesh.n_elem
+        self.n_face = mesh.n_face
+        self.N_uh = int(self.layout["face_off"][-1])
+
+    def _layout(self, kind):
+        n = self.L.hdg_layout_length(self.h, kind)
+        out = np.zeros(max(n, 1), dtype=np.int64)
+        _check(self.L.hdg_layout(self.h, kind, out.ctypes.data, n), "hdg_layout")
+        return out[:n]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.hdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- sizes
+    def workspace_size(self, op, prec=HDG_FP64, e0=0, ne=None):
+        ne = self.n_elem if ne is None else ne
+        out = ctypes.c_size_t()
+        _check(self.L.hdg_workspace_size(self.h, op, prec, e0, ne, ctypes.byref(out)), "hdg_workspace_size")
+        return out.value
+
+    def e_size(self, e0, ne):
+        if e0 < 0 or ne < 1 or e0 + ne > self.n_elem:
+            return 0  # the library rejects the chunk itself
+        return int(self.layout["E_off"][e0 + ne] - self.layout["E_off"][e0])
+
+    # ------------------------------------------------------ entry points
+    def hdg_local_residual_jacobian(self, e0, ne, Q, U, Un, Uhat, nu, Ub, E, work, stream=None):
+        import torch
+        f64 = torch.float64
+        nn = int(self.layout["node_off"][-1])
+        rc = self.L.hdg_local_residual_jacobian(
+            self.h, e0, ne, _ptr(Q, f64, 15 * nn, "Q"), _ptr(U, f64, 5 * nn, "U"), _ptr(Un, f64, 5 * nn, "Un"),
+            _ptr(Uhat, f64, self.N_uh, "Uhat"), _ptr(nu, f64, nn, "nu"),
+            _ptr(Ub, f64, self.N_uh, "Ub") if Ub is not None else None,
+            _ptr(E, f64, self.e_size(e0, ne), "E"), _ptr(work, None, None, "work"),
+            work.numel() * work.element_size(), _stream(stream))
+        _check(rc, "hdg_local_residual_jacobian")
+
+    def hdg_condense(self, prec, refine_steps, e0, ne, E, SK, info, work, stream=None):
+        import torch
+        rc = self.L.hdg_condense(self.h, prec, refine_steps, e0, ne, _ptr(E, torch.float64, self.e_size(e0, ne), "E"),
+                                 _ptr(SK, torch.float64, int(self.layout["SK_off"][-1]), "SK"),
+                                 _ptr(info, torch.int32, self.n_elem, "info"), _ptr(work, None, None, "work"),
+                                 work.numel() * work.element_size(), _stream(stream))
+        _check(rc, "hdg_condense")
+
+    def hdg_assemble_trace(self, SK, S, g, stream=None):
+        import torch
+        rc = self.L.hdg_assemble_trace(self.h, _ptr(SK, torch.float64, int(self.layout["SK_off"][-1]), "SK"),
+                                       _ptr(S, torch.float64, int(self.layout["bsr_val_off"][-1]), "S"),
+                                       _ptr(g, torch.float64, self.N_uh, "g"), _stream(stream))
+        _check(rc, "hdg_assemble_trace")
+
+    def hdg_face_matvec(self, S, x, y, stream=None):
+        import torch
+        rc = self.L.hdg_face_matvec(self.h, _ptr(S, torch.float64, int(self.layout["bsr_val_off"][-1]), "S"),
+                                    _ptr(x, torch.float64, self.N_uh, "x"), _ptr(y, torch.float64, self.N_uh, "y"),
+                                    _stream(stream))
+        _check(rc, "hdg_face_matvec")
+
+    def _sinv_dtype(self, prec):
+        import torch
+        return torch.float64 if prec == HDG_FP64 else torch.float32
+
+    def hdg_asm_setup(self, prec, S, Sinv, info, work, stream=None):
+        import torch
+        rc = self.L.hdg_asm_setup(self.h, prec, _ptr(S, torch.float64, int(self.layout["bsr_val_off"][-1]), "S"),
+                                  _ptr(Sinv, self._sinv_dtype(prec), int(self.layout["asm_off"][-1]), "Sinv"),
+                                  _ptr(info, torch.int32, self.n_elem, "info"), _ptr(work, None, None, "work"),
+                                  work.numel() * work.element_size(), _stream(stream))
+        _check(rc, "hdg_asm_setup")
+
+    def hdg_asm_block_apply(self, prec, Sinv, r, z, work, stream=None):
+        import torch
+        rc = self.L.hdg_asm_block_apply(self.h, prec,
+                                        _ptr(Sinv, self._sinv_dtype(prec), int(self.layout["asm_off"][-1]), "Sinv"),
+                                        _ptr(r, torch.float64, self.N_uh, "r"), _ptr(z, torch.float64, self.N_uh, "z"),
+                                        _ptr(work, None, None, "work"), work.numel() * work.element_size(),
+                                        _stream(stream))
+        _check(rc, "hdg_asm_block_apply")
+
+    def hdg_gmres(self, prec, S, Sinv, g, m, dUhat, res_hist, work, stream=None):
+        import torch
+        rc = self.L.hdg_gmres(self.h, prec, _ptr(S, torch.float64, int(self.layout["bsr_val_off"][-1]), "S"),
+                              _ptr(Sinv, self._sinv_dtype(prec), int(self.layout["asm_off"][-1]), "Sinv"),
+                              _ptr(g, torch.float64, self.N_uh, "g"), int(m),
+                              _ptr(dUhat, torch.float64, self.N_uh, "dUhat"),
+                              _ptr(res_hist, torch.float64, m + 1, "res_hist"), _ptr(work, None, None, "work"),
+                              work.numel() * work.element_size(), _stream(stream))
+        _check(rc, "hdg_gmres")
+
+    def hdg_recover_interior(self, prec, e0, ne, E, dUhat, dQU, stream=None):
+        import torch
+        nn = int(self.layout["node_off"][-1])
+        rc = self.L.hdg_recover_interior(self.h, prec, e0, ne, _ptr(E, torch.float64, self.e_size(e0, ne), "E"),
+                                         _ptr(dUhat, torch.float64, self.N_uh, "dUhat"),
+                                         _ptr(dQU, torch.float64, 20 * nn, "dQU"), _stream(stream))
+        _check(rc, "hdg_recover_interior")

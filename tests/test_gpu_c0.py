@@ -1,0 +1,156 @@
+"""GPU parity, full 4^3 periodic TGV mesh at p=2 (64 elements): every step of
+the HIP path against the CPU oracle, element by element, at the FP64 bound."""
+import numpy as np
+import pytest
+
+from gpu_common import (O, RTOL_FP64, assembled_g_scale, assert_rel, bsr_blocks, e_view, oracle_condensed, rel_err,
+                        recovery_checks, recovery_error, residual_scale, sk_view)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c0():
+    import torch
+    from paper_2608_27863_amd import pipeline, synth
+    wl = synth.config(0)
+    print("[c0] building the Newton step on cuda:0", flush=True)
+    st = pipeline.NewtonStep(wl)
+    st.residual_jacobian()
+    torch.cuda.synchronize()
+    E = st.E.cpu().numpy()
+    print("[c0] element systems done; condensing", flush=True)
+    st.condense()
+    st.assemble()
+    torch.cuda.synchronize()
+    print("[c0] condensed; Schwarz + GMRES + recovery", flush=True)
+    st.asm_setup()
+    st.gmres()
+    st.recover()
+    torch.cuda.synchronize()
+    gpu = dict(E=E, SK=st.SK.cpu().numpy(), S=st.S.cpu().numpy(), g=st.g.cpu().numpy(),
+               dUhat=st.dUhat.cpu().numpy(), hist=st.hist.cpu().numpy(), dQU=st.dQU.cpu().numpy(),
+               info=st.info.cpu().numpy(), asm_info=st.asm_info.cpu().numpy())
+    print("[c0] oracle", flush=True)
+    ora = oracle_condensed(wl)
+    ts = O.TraceSystem(wl, [ora[e]["SK"] for e in range(wl.mesh.n_elem)],
+                       [ora[e]["gK"] for e in range(wl.mesh.n_elem)])
+    x_ora, hist_ora = O.gmres(ts, ts.g, wl.gmres_m)
+    return dict(wl=wl, st=st, gpu=gpu, ora=ora, ts=ts, x=x_ora, hist=hist_ora)
+
+
+def test_element_systems(c0):
+    st, gpu, ora = c0["st"], c0["gpu"], c0["ora"]
+    ctx = st.ctx
+    worst = {}
+    for e in range(c0["wl"].mesh.n_elem):
+        Eg, ld = e_view(ctx, gpu["E"], e)
+        Eo = ora[e]["E"]
+        n = int(ctx.layout["elem_n"][e])
+        full = gpu["E"][int(ctx.layout["E_off"][e]):int(ctx.layout["E_off"][e + 1])].reshape(Eg.shape[0], ld)
+        assert np.all(full[:, Eg.shape[1]:] == 0.0), "padding columns must be zero"
+        for name, gb, ob in zip("A B C D".split(), O.split(Eg, n)[:4], O.split(Eo, n)[:4]):
+            worst[name] = max(worst.get(name, 0.0), rel_err(gb, ob))
+        # residual columns: rounding relative to the magnitude of their summands
+        scale = residual_scale(c0["wl"], ctx, e, Eo)
+        for name, rows in (("Rqu", slice(0, n)), ("Ruh", slice(n, None))):
+            d = np.linalg.norm(Eg[rows, -1] - Eo[rows, -1]) / np.linalg.norm(scale[rows])
+            worst[name] = max(worst.get(name, 0.0), d)
+    print("  worst per block:", {k: f"{v:.2e}" for k, v in worst.items()})
+    for name, v in worst.items():
+        assert v <= RTOL_FP64, f"block {name}: {v:.3e}"
+
+
+def test_condensed_elements(c0):
+    st, gpu, ora = c0["st"], c0["gpu"], c0["ora"]
+    assert np.all(gpu["info"] == 0)
+    ws, wg = 0.0, 0.0
+    for e in range(c0["wl"].mesh.n_elem):
+        S, g = sk_view(st.ctx, gpu["SK"], e)
+        ws = max(ws, rel_err(S, ora[e]["SK"]))
+        wg = max(wg, rel_err(g, ora[e]["gK"]))
+    print(f"  max over elements: S^K {ws:.3e}  g^K {wg:.3e}")
+    assert ws <= RTOL_FP64 and wg <= RTOL_FP64
+
+
+def test_assembled_trace_system(c0):
+    st, gpu, ts = c0["st"], c0["gpu"], c0["ts"]
+    blocks = bsr_blocks(st.ctx, gpu["S"])
+    assert set(blocks) == set(ts.blocks), "block-sparse pattern differs from the element coupling"
+    num = sum(np.linalg.norm(blocks[k] - ts.blocks[k]) ** 2 for k in blocks) ** 0.5
+    den = sum(np.linalg.norm(ts.blocks[k]) ** 2 for k in blocks) ** 0.5
+    print(f"  S: {num / den:.3e}")
+    assert num / den <= RTOL_FP64
+    gs = assembled_g_scale(c0["wl"], [c0["ora"][e]["gK"] for e in range(c0["wl"].mesh.n_elem)])
+    eg = np.linalg.norm(gpu["g"] - ts.g) / np.linalg.norm(gs)
+    print(f"  g: {np.linalg.norm(gpu['g'] - ts.g) / np.linalg.norm(ts.g):.3e} of |g|, {eg:.3e} of sum |g^K|")
+    assert eg <= RTOL_FP64
+
+
+def test_face_matvec(c0):
+    import torch
+    st, ts, wl = c0["st"], c0["ts"], c0["wl"]
+    x = torch.as_tensor(wl.x, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    st.ctx.hdg_face_matvec(st.S, x, y)
+    assert_rel(y.cpu().numpy(), ts.matvec(wl.x), RTOL_FP64, "S x")
+
+
+def test_asm_apply(c0):
+    import torch
+    st, ts, wl = c0["st"], c0["ts"], c0["wl"]
+    assert np.all(c0["gpu"]["asm_info"] == 0)
+    x = torch.as_tensor(wl.x, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(x)
+    work = torch.empty(st.ctx.workspace_size(3), dtype=torch.uint8, device="cuda")
+    st.ctx.hdg_asm_block_apply(0, st.Sinv, x, z, work)
+    assert_rel(z.cpu().numpy(), ts.asm_apply(wl.x), RTOL_FP64, "M^-1 x")
+
+
+def test_gmres_same_inputs(c0):
+    """GMRES(30) on identical S and g: the GPU (CGS2, explicit Schwarz inverses)
+    against the oracle (MGS, LU solves of the Schwarz blocks)."""
+    st, gpu, wl = c0["st"], c0["gpu"], c0["wl"]
+    ts = O.TraceSystem.from_blocks(wl, bsr_blocks(st.ctx, gpu["S"]), gpu["g"])
+    x, hist = O.gmres(ts, ts.g, wl.gmres_m)
+    assert_rel(gpu["dUhat"], x, RTOL_FP64, "dUhat, same S and g")
+    h = gpu["hist"]
+    assert h.shape == hist.shape
+    # below ~1e-13 of the initial residual both histories are rounding noise
+    live = hist > 1e-12 * hist[0]
+    assert np.max(np.abs(h[live] - hist[live]) / hist[live]) <= 1e-8
+    assert np.all(np.diff(h) <= 1e-14 * h[0])
+
+
+def test_gmres_end_to_end(c0):
+    """Whole chain against the oracle's own S and g: the increment inherits the
+    rounding of g (a sum of cancelling element terms), amplified by the solve."""
+    gpu = c0["gpu"]
+    e = assert_rel(gpu["dUhat"], c0["x"], 1e-10, "dUhat end to end")
+    assert e <= 1e-10
+
+
+def test_recovery(c0):
+    wl, st, gpu, ora = c0["wl"], c0["st"], c0["gpu"], c0["ora"]
+    sz = O.Sizes(wl.mesh)
+    no = st.ctx.layout["node_off"]
+    wb, wf, wp = 0.0, 0.0, 0.0
+    for e in range(wl.mesh.n_elem):
+        got = gpu["dQU"][20 * int(no[e]):20 * int(no[e + 1])]
+        b, fr = recovery_checks(wl, e, ora[e]["E"], ora[e]["X"], gpu["dUhat"], got)
+        _, ep = recovery_error(wl, e, ora[e]["X"], gpu["dUhat"], got)
+        wb, wf, wp = max(wb, b), max(wf, fr), max(wp, ep)
+    print(f"  d(Q,U): backward error {wb:.2f} of n u, forward error {wf:.2f} of its bound, {wp:.2e} of its norm")
+    assert wb <= 1.0 and wf <= 1.0
+
+
+def test_bitwise_reproducible_and_chunk_independent(c0):
+    import torch
+    from paper_2608_27863_amd import pipeline
+    wl, gpu = c0["wl"], c0["gpu"]
+    st2 = pipeline.NewtonStep(wl, chunk=13, ctx=c0["st"].ctx)  # ragged chunks: 13,13,13,13,12
+    st2.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(st2.SK.cpu().numpy(), gpu["SK"])
+    assert np.array_equal(st2.dUhat.cpu().numpy(), gpu["dUhat"])
+    assert np.array_equal(st2.dQU.cpu().numpy(), gpu["dQU"])
