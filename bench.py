@@ -1,0 +1,183 @@
+"""Benchmark of the HDG hot path on one MI355X.
+
+One step = one Newton step of the whole hot path on the 8^3 periodic
+supersonic Taylor-Green workload at p = 3 (512 hexahedra, n = 1280 interior and
+f = 480 trace unknowns per element): element residuals and Jacobians,
+condensation, trace assembly, additive-Schwarz set-up, 30 GMRES iterations and
+interior recovery, all inputs resident in HBM.
+
+Prints one JSON line: whole-step throughput in elements/s, the condensation
+roofline (FP64 MFMA), the face-matvec roofline (HBM), and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
+
+
+def condense_flops_per_element(n, f):
+    """Dense condensation as specified: LU of A (2n^3/3), solve with n x (f+1)
+    right-hand sides (2n^2(f+1)), Schur product C X (2fn(f+1))."""
+    return 2.0 * n ** 3 / 3.0 + 2.0 * n * n * (f + 1) + 2.0 * f * n * (f + 1)
+
+
+def matvec_bytes(ctx):
+    """Algorithmic bytes of y = S x: S read once, block-sparse indices, x read
+    once, y written once."""
+    import numpy as np
+    vo = ctx.layout["bsr_val_off"]
+    nnzb = len(ctx.layout["bsr_col"])
+    return 8.0 * float(vo[-1]) + 4.0 * nnzb + 4.0 * (ctx.n_face + 1) + 2.0 * 8.0 * ctx.N_uh
+
+
+def cpu_baseline(wl, seconds=15.0):
+    """The oracle (plain C element systems + textbook LU condensation) on the
+    host cores, on a sample of the benchmark's elements."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    O.build()
+    sz = O.Sizes(wl.mesh)
+    cores = max(1, min(16, os.cpu_count() or 1))
+
+    def one(e):
+        E = O.element_system(wl, e, sz)
+        O.condense(E, sz.n(e))
+
+    # calibrate on one element, then size the sample to ~`seconds` of work
+    t0 = time.perf_counter()
+    one(0)
+    t1 = time.perf_counter() - t0
+    per_wave = max(t1, 1e-3)
+    waves = max(1, int(seconds / per_wave))
+    count = min(wl.mesh.n_elem, cores * waves)
+    elems = list(range(count))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(one, elems))
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "elements/s", "cores": cores, "kind": "oracle",
+            "sample": f"element residual+Jacobian and condensation of elements 0..{count - 1} "
+                      f"({count} of {wl.mesh.n_elem}) of the same workload; trace assembly, Schwarz and GMRES "
+                      f"excluded; {dt:.1f} s wall on {cores} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU's partition only (--gpus {args.gpus} requested); "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2608_27863_amd import hdg, pipeline, synth
+
+    wl = synth.config(1)
+    print(f"[bench] workload {wl.name}: building context", file=sys.stderr, flush=True)
+    st = pipeline.NewtonStep(wl, prec=hdg.HDG_FP64)
+    ctx = st.ctx
+    ne = ctx.n_elem
+    n, f = int(ctx.layout["elem_n"][0]), int(ctx.layout["elem_f"][0])
+    stream = torch.cuda.current_stream()
+    phases = ["residual_jacobian", "condense", "assemble", "asm_setup", "gmres", "recover"]
+
+    def step(events=None):
+        for i, ph in enumerate(phases):
+            if events is not None:
+                events[i].record(stream)
+            getattr(st, ph)()
+        if events is not None:
+            events[-1].record(stream)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    if not np.all(st.info.cpu().numpy() == 0) or not np.all(st.asm_info.cpu().numpy() == 0):
+        raise RuntimeError("zero pivot reported during the warm-up")
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    phase_ms = {ph: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
+                for i, ph in enumerate(phases)}
+    print(f"[bench] {args.steps} timed steps: {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # condensation roofline (FP64 MFMA): dense algorithmic flops / hdg_condense time
+    fl = condense_flops_per_element(n, f) * ne
+    t_cond = phase_ms["condense"] * 1e-3
+    achieved = fl / t_cond / 1e12
+
+    # face matvec roofline (HBM): algorithmic bytes / kernel time, alternating buffers
+    x0 = torch.as_tensor(wl.x, dtype=torch.float64, device="cuda")
+    xs = [x0, x0.clone()]
+    ys = [torch.empty_like(x0) for _ in range(2)]
+    for _ in range(3):
+        ctx.hdg_face_matvec(st.S, xs[0], ys[0])
+    reps = 50
+    mv_ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    mv_ev[0].record(stream)
+    for r in range(reps):
+        ctx.hdg_face_matvec(st.S, xs[r % 2], ys[r % 2])
+        mv_ev[r + 1].record(stream)
+    torch.cuda.synchronize()
+    mv_ms = float(np.mean([mv_ev[r].elapsed_time(mv_ev[r + 1]) for r in range(reps)]))
+    mv_bytes = matvec_bytes(ctx)
+    mv_gbps = mv_bytes / (mv_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "HDG condensed elements/s, FP64 vs mixed @1e-10 rel; face-matvec GB/s",
+        "value": ne / (ms_step * 1e-3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "elements": ne, "p": 3, "n_interior": n, "f_trace": f,
+                   "gmres_iterations": st.m, "schwarz": "element-block, FP64", "precision": "FP64",
+                   "step": "residual+Jacobian, condensation, assembly, Schwarz set-up, GMRES(30), recovery"},
+        "condense_elements_per_s": ne / t_cond,
+        "phase_ms": phase_ms,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "hdg_condense (k_panel, k_swap_trsm, k_update per 64-column panel; k_extract)",
+                     "algorithmic": f"{condense_flops_per_element(n, f):.4e} flop/element x {ne} elements"},
+        "roofline_matvec": {"bound": "hbm", "achieved": mv_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                            "frac": mv_gbps / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_matvec",
+                            "ms": mv_ms, "algorithmic_bytes": mv_bytes},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
