@@ -313,28 +313,6 @@ __global__ void __launch_bounds__(64) k_qp_face(DevMesh dm, Phys P, int e0, cons
 }
 
 // --------------------------------------------------------- assembly kernel
-// Reference-element helpers working on LDS copies of the 1-D tables.
-struct Ref {
-    int p, p1, nq, Np, Nq;
-    const double *L;   // [a][g] values at the volume Gauss points
-    const double *D;   // [a][g] derivatives
-    __device__ inline double phi(int i, int g) const {
-        const int i0 = i % p1, i1 = (i / p1) % p1, i2 = i / (p1 * p1);
-        const int g0 = g % nq, g1 = (g / nq) % nq, g2 = g / (nq * nq);
-        return L[i0 * nq + g0] * L[i1 * nq + g1] * L[i2 * nq + g2];
-    }
-    // value (d = 0) or reference derivative d-1 of phi_i at point g
-    __device__ inline void phi_all(int i, int g, double out[4]) const {
-        const int i0 = i % p1, i1 = (i / p1) % p1, i2 = i / (p1 * p1);
-        const int g0 = g % nq, g1 = (g / nq) % nq, g2 = g / (nq * nq);
-        const double l0 = L[i0 * nq + g0], l1 = L[i1 * nq + g1], l2 = L[i2 * nq + g2];
-        out[0] = l0 * l1 * l2;
-        out[1] = D[i0 * nq + g0] * l1 * l2;
-        out[2] = l0 * D[i1 * nq + g1] * l2;
-        out[3] = l0 * l1 * D[i2 * nq + g2];
-    }
-};
-
 // Face of an element: is volume node i on local face lf, and its face indices.
 __device__ inline bool on_face(int i, int p1, int lf, int &a0, int &a1) {
     const int d = lf / 2, side = lf & 1;
@@ -346,33 +324,20 @@ __device__ inline bool on_face(int i, int p1, int lf, int &a0, int &a1) {
     return true;
 }
 
-constexpr int kCh = 32;  // quadrature points per LDS chunk
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int T>
-__global__ void __launch_bounds__(256) k_assemble_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
-                                                       double *__restrict__ Ebase) {
-    const int e = e0 + blockIdx.y;
-    const int rb = blockIdx.x;  // 0..19 interior row field, 20..25 trace rows of face rb-20
-    const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
-    const int *toff = dm.toff + 7 * e;
-    const int n = 20 * Np, f = toff[6];
-    const int64_t ld = e_ld(n, f);
-    double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
-    const double *qpe = qp + (dm.qp_off[e] - dm.qp_off[e0]);
-    const double *vg = dm.vgeo + dm.vgeo_off[e];
+constexpr int kKC = 32;       // quadrature points per LDS chunk
+
+// Shared set-up of the element-row kernels: 1-D tables of the element and of
+// its faces, face quadrature bases in the point workspace.
+struct RowSetup {
+    int p, p1, Np, nq, Nq, n, f;
+    int64_t ld;
+};
+
+__device__ inline void load_face_tables(const DevMesh &dm, int e, int p, int Nq, double (*sLf)[30],
+                                        double (*sMf)[30], int *sPf, int *sNqf, int64_t *sFbase) {
     const int tid = threadIdx.x;
-
-    __shared__ double sL[30], sD[30];
-    __shared__ double sLf[6][30], sMf[6][30];  // element basis / trace basis at each face's points
-    __shared__ int sPf[6], sNqf[6];
-    __shared__ int64_t sFbase[6];
-    __shared__ double sH[128 * kCh], sP[128 * kCh];
-    __shared__ double sFc[6 * 36];           // face coefficient of the current block
-    __shared__ double sFB[6 * 5 * 36];        // face coefficients of the B columns
-    for (int t = tid; t < p1 * nq; t += blockDim.x) {
-        sL[t] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
-        sD[t] = dm.tbl[tbl_D(p, t / nq, t % nq)];
-    }
     if (tid < 6) {
         const int pf = dm.face_p[dm.elem_face[6 * e + tid]];
         sPf[tid] = pf;
@@ -383,13 +348,63 @@ __global__ void __launch_bounds__(256) k_assemble_rows(DevMesh dm, Phys P, int e
     for (int t = tid; t < 6 * 30; t += blockDim.x) {
         const int lf = t / 30, r = t % 30, pf = sPf[lf], nqf1 = pf + 2;
         const int a = r / nqf1, s = r % nqf1;
-        sLf[lf][r] = (a <= p && s < nqf1 && r < (p + 1) * nqf1) ? dm.tbl[tbl_L(p, pf, a, s)] : 0.0;
-        sMf[lf][r] = (a <= pf && r < (pf + 1) * nqf1) ? dm.tbl[tbl_L(pf, pf, a, s)] : 0.0;
+        sLf[lf][r] = (r < (p + 1) * nqf1) ? dm.tbl[tbl_L(p, pf, a, s)] : 0.0;
+        sMf[lf][r] = (r < (pf + 1) * nqf1) ? dm.tbl[tbl_L(pf, pf, a, s)] : 0.0;
     }
-    __syncthreads();
-    Ref R{p, p1, nq, Np, Nq, sL, sD};
+}
 
-    // value of the element basis phi_i at point s of face lf (i on that face)
+// Interior rows of the element system.  blockIdx.x: 0..2 = gradient rows of
+// direction j (fields 3c+j, c = 0..4: the mass block and the block
+// int phi_k d_j phi_i are the same for every c), 3..7 = conservation rows of
+// component c.  Each Np x Np block is sum_g phi_k(g) [c0 phi_i + c_d dref_d phi_i](g),
+// formed with FP64 MFMA from LDS chunks of the point coefficients.
+template <int T>
+__global__ void __launch_bounds__(256) k_assemble_interior(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
+                                                           double *__restrict__ Ebase) {
+    constexpr int RB = (T >= 4) ? T / 4 : 1;  // 16-row blocks per wave
+    constexpr int CB = (T >= 4) ? T : 1;      // 16-column blocks per wave
+    constexpr int KC = (T == 8) ? 16 : kKC;   // quadrature points per chunk
+    constexpr int HS = KC + 2;                // LDS row stride
+    constexpr int NR = 16 * T;                // padded basis count
+    const int e = e0 + blockIdx.y, rb = blockIdx.x;
+    const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
+    const int *toff = dm.toff + 7 * e;
+    const int n = 20 * Np, f = toff[6];
+    const int64_t ld = e_ld(n, f);
+    double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    const double *qpe = qp + (dm.qp_off[e] - dm.qp_off[e0]);
+    const double *vg = dm.vgeo + dm.vgeo_off[e];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool qrows = rb < 3;
+    const int jdir = qrows ? rb : 0, cu = qrows ? 0 : rb - 3;
+
+    __shared__ double sL[30], sD[30];
+    __shared__ double sLf[6][30], sMf[6][30];
+    __shared__ int sPf[6], sNqf[6];
+    __shared__ int64_t sFbase[6];
+    __shared__ unsigned short s_ix[128], s_gx[216];
+    __shared__ double sH[NR][HS], sP[NR][HS];
+    __shared__ double sC[4][KC];
+    __shared__ double sFc[6 * 36];
+    __shared__ double sFB[6 * 5 * 36];
+    for (int t = tid; t < p1 * nq; t += blockDim.x) {
+        sL[t] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
+        sD[t] = dm.tbl[tbl_D(p, t / nq, t % nq)];
+    }
+    for (int t = tid; t < Np; t += blockDim.x) s_ix[t] = (unsigned short)((t % p1) | (((t / p1) % p1) << 4) | ((t / (p1 * p1)) << 8));
+    for (int t = tid; t < Nq; t += blockDim.x) s_gx[t] = (unsigned short)((t % nq) | (((t / nq) % nq) << 4) | ((t / (nq * nq)) << 8));
+    load_face_tables(dm, e, p, Nq, sLf, sMf, sPf, sNqf, sFbase);
+    __syncthreads();
+
+    auto on_face_ix = [&](int i, int lf, int &a0, int &a1) {
+        const int code = s_ix[i];
+        const int idx[3] = {code & 15, (code >> 4) & 15, code >> 8};
+        const int d = lf >> 1;
+        if (idx[d] != ((lf & 1) ? p : 0)) return false;
+        a0 = idx[d == 0 ? 1 : 0];
+        a1 = idx[d == 2 ? 1 : 2];
+        return true;
+    };
     auto phi_face = [&](int lf, int a0, int a1, int s) {
         const int nqf1 = sPf[lf] + 2;
         return sLf[lf][a0 * nqf1 + (s % nqf1)] * sLf[lf][a1 * nqf1 + (s / nqf1)];
@@ -399,102 +414,137 @@ __global__ void __launch_bounds__(256) k_assemble_rows(DevMesh dm, Phys P, int e
         return sMf[lf][(b % pf1) * nqf1 + (s % nqf1)] * sMf[lf][(b / pf1) * nqf1 + (s / nqf1)];
     };
 
-    if (rb < 20) {
-        // ================= interior rows of field rb
-        const int r = rb;
-        const bool qrow = r < 15;
-        const int c = qrow ? r / 3 : r - 15, j = qrow ? r % 3 : 0;
-        double *Er = E + (int64_t)r * Np * ld;
-        // register tile: thread (ti, tk) owns rows ti + 16a, cols tk + 16b (T = ceil(max N_p / 16))
-        const int ti = tid / 16, tk = tid % 16;
-        for (int sblk = 0; sblk < 20; ++sblk) {
-            __syncthreads();  // previous block's readers of sFc are done
-            bool nonzero = qrow ? (sblk == r || sblk == 15 + c) : true;
-            if (!nonzero) {
-                for (int t = tid; t < Np * Np; t += blockDim.x) Er[(int64_t)(t / Np) * ld + sblk * Np + t % Np] = 0.0;
-                continue;
-            }
-            // face coefficients of this block (conservation rows only)
-            if (!qrow) {
-                const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
-                for (int t = tid; t < 6 * 36; t += blockDim.x) {
-                    const int lf = t / 36, s = t % 36;
-                    sFc[t] = (s < sNqf[lf]) ? P.dt * qpe[sFbase[lf] + (int64_t)(25 * c + slot) * sNqf[lf] + s] : 0.0;
+    d4 acc[RB][CB];
+    // kind: 0 = mass (W), 1 = int phi_k d_j phi_i (W G[d][j]), 2 = conservation row cu, column field sblk
+    auto block_product = [&](int kind, int sblk) {
+#pragma unroll
+        for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int g0 = 0; g0 < Nq; g0 += KC) {
+            __syncthreads();
+            if (tid < 4 * KC) {
+                const int d = tid / KC, gg = tid % KC, g = g0 + gg;
+                double v = 0.0;
+                if (g < Nq) {
+                    if (kind == 0) v = (d == 0) ? vg[g] : 0.0;
+                    else if (kind == 1) v = (d == 0) ? 0.0 : vg[g] * vg[(1 + 3 * (d - 1) + jdir) * Nq + g];
+                    else v = qpe[(int64_t)(4 * (20 * cu + sblk) + d) * Nq + g];
                 }
+                sC[d][gg] = v;
             }
-            double acc[T][T];
+            __syncthreads();
+#pragma unroll 4
+            for (int q = 0; q < (NR * KC + 255) / 256; ++q) {
+                const int t = tid + 256 * q;
+                if (t >= NR * KC) break;
+                const int i = t / KC, gg = t % KC, g = g0 + gg;
+                double h = 0.0, ph = 0.0;
+                if (i < Np && g < Nq) {
+                    const int ci = s_ix[i], cg = s_gx[g];
+                    const int a0 = (ci & 15) * nq + (cg & 15), a1 = ((ci >> 4) & 15) * nq + ((cg >> 4) & 15),
+                              a2 = (ci >> 8) * nq + (cg >> 8);
+                    const double l0 = sL[a0], l1 = sL[a1], l2 = sL[a2];
+                    ph = l0 * l1 * l2;
+                    h = sC[0][gg] * ph + sC[1][gg] * sD[a0] * l1 * l2 + sC[2][gg] * l0 * sD[a1] * l2 +
+                        sC[3][gg] * l0 * l1 * sD[a2];
+                }
+                sH[i][gg] = h;
+                sP[i][gg] = ph;
+            }
+            __syncthreads();
+            if (T >= 2 || wave == 0) {
 #pragma unroll
-            for (int a = 0; a < T; ++a)
+                for (int kk = 0; kk < KC; kk += 4) {
+                    double av[RB];
 #pragma unroll
-                for (int b = 0; b < T; ++b) acc[a][b] = 0.0;
-            for (int g0 = 0; g0 < Nq; g0 += kCh) {
-                const int gn = min(kCh, Nq - g0);
-                __syncthreads();
-                for (int t = tid; t < 128 * kCh; t += blockDim.x) {
-                    const int i = t / kCh, gg = t % kCh, g = g0 + gg;
-                    double h = 0.0, ph = 0.0;
-                    if (i < Np && gg < gn) {
-                        double v[4];
-                        R.phi_all(i, g, v);
-                        ph = v[0];
-                        if (qrow) {
-                            if (sblk == r) h = vg[g] * v[0];
-                            else h = vg[g] * (vg[(1 + j) * Nq + g] * v[1] + vg[(4 + j) * Nq + g] * v[2] + vg[(7 + j) * Nq + g] * v[3]);
-                        } else {
-                            const double *cf = qpe + (int64_t)(4 * (20 * c + sblk)) * Nq + g;
-                            h = cf[0] * v[0] + cf[Nq] * v[1] + cf[2 * Nq] * v[2] + cf[3 * Nq] * v[3];
-                        }
+                    for (int a = 0; a < RB; ++a) {
+                        const int bi = (T >= 4) ? wave * RB + a : ((T == 2) ? (wave >> 1) : 0);
+                        av[a] = sH[16 * bi + (lane & 15)][kk + (lane >> 4)];
                     }
-                    sH[t] = h;
-                    sP[t] = ph;
-                }
-                __syncthreads();
-                for (int gg = 0; gg < gn; ++gg) {
-                    double hv[T], pv[T];
 #pragma unroll
-                    for (int a = 0; a < T; ++a) hv[a] = sH[(ti + 16 * a) * kCh + gg];
+                    for (int b = 0; b < CB; ++b) {
+                        const int bj = (T >= 4) ? b : ((T == 2) ? (wave & 1) : 0);
+                        const double bv = sP[16 * bj + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-                    for (int b = 0; b < T; ++b) pv[b] = sP[(tk + 16 * b) * kCh + gg];
-#pragma unroll
-                    for (int a = 0; a < T; ++a)
-#pragma unroll
-                        for (int b = 0; b < T; ++b) acc[a][b] += hv[a] * pv[b];
+                        for (int a = 0; a < RB; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv, acc[a][b], 0, 0, 0);
+                    }
                 }
             }
-            __syncthreads();  // sFc ready (written before the chunk loop's first barrier)
+        }
+    };
+    // write the block (plus face terms of the conservation rows) to rows of field r
+    auto write_block = [&](int r, int sblk, bool faces) {
+        if (!(T >= 2 || wave == 0)) return;
 #pragma unroll
-            for (int a = 0; a < T; ++a) {
-                const int i = ti + 16 * a;
-                if (i >= Np) continue;
+        for (int a = 0; a < RB; ++a)
 #pragma unroll
-                for (int b = 0; b < T; ++b) {
-                    const int k = tk + 16 * b;
-                    if (k >= Np) continue;
-                    double v = acc[a][b];
-                    if (!qrow) {
+            for (int b = 0; b < CB; ++b) {
+                const int bi = (T >= 4) ? wave * RB + a : ((T == 2) ? (wave >> 1) : 0);
+                const int bj = (T >= 4) ? b : ((T == 2) ? (wave & 1) : 0);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int i = 16 * bi + 4 * jj + (lane >> 4), k = 16 * bj + (lane & 15);
+                    if (i >= Np || k >= Np) continue;
+                    double v = acc[a][b][jj];
+                    if (faces) {
                         for (int lf = 0; lf < 6; ++lf) {
                             int ia0, ia1, ka0, ka1;
-                            if (!on_face(i, p1, lf, ia0, ia1) || !on_face(k, p1, lf, ka0, ka1)) continue;
+                            if (!on_face_ix(i, lf, ia0, ia1) || !on_face_ix(k, lf, ka0, ka1)) continue;
                             for (int s = 0; s < sNqf[lf]; ++s)
                                 v += sFc[lf * 36 + s] * phi_face(lf, ia0, ia1, s) * phi_face(lf, ka0, ka1, s);
                         }
                     }
-                    Er[(int64_t)i * ld + sblk * Np + k] = v;
+                    E[(int64_t)(r * Np + i) * ld + sblk * Np + k] = v;
                 }
             }
+    };
+    auto zero_block = [&](int r, int sblk) {
+        for (int t = tid; t < Np * Np; t += blockDim.x) E[(int64_t)(r * Np + t / Np) * ld + sblk * Np + t % Np] = 0.0;
+    };
+
+    if (qrows) {
+        // mass blocks on the diagonal of every gradient row field of direction jdir
+        block_product(0, 0);
+        for (int c = 0; c < 5; ++c) write_block(3 * c + jdir, 3 * c + jdir, false);
+        block_product(1, 0);
+        for (int c = 0; c < 5; ++c) write_block(3 * c + jdir, 15 + c, false);
+        for (int c = 0; c < 5; ++c) {
+            const int r = 3 * c + jdir;
+            for (int sblk = 0; sblk < 20; ++sblk)
+                if (sblk != r && sblk != 15 + c) zero_block(r, sblk);
         }
-        // ---- B columns: face lf, component cp, trace node b
+    } else {
+        const int slotbase = 0;
+        (void)slotbase;
+        for (int sblk = 0; sblk < 20; ++sblk) {
+            __syncthreads();
+            const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
+            for (int t = tid; t < 6 * 36; t += blockDim.x) {
+                const int lf = t / 36, s = t % 36;
+                sFc[t] = (s < sNqf[lf]) ? P.dt * qpe[sFbase[lf] + (int64_t)(25 * cu + slot) * sNqf[lf] + s] : 0.0;
+            }
+            block_product(2, sblk);
+            write_block(15 + cu, sblk, true);
+        }
+    }
+    // ---- B columns (face lf, component cp, trace node b) and residual/padding columns
+    const int nfield = qrows ? 5 : 1;
+    for (int fi = 0; fi < nfield; ++fi) {
+        const int c = qrows ? fi : cu;
+        const int r = qrows ? 3 * fi + jdir : 15 + cu;
         __syncthreads();
         for (int t = tid; t < 6 * 5 * 36; t += blockDim.x) {
             const int lf = t / 180, cp = (t / 36) % 5, s = t % 36;
             double v = 0.0;
             if (s < sNqf[lf]) {
-                if (qrow) v = (cp == c) ? -dm.fgeo[dm.fgeo_off[6 * e + lf] + (int64_t)j * sNqf[lf] + s] : 0.0;
+                if (qrows) v = (cp == c) ? -dm.fgeo[dm.fgeo_off[6 * e + lf] + (int64_t)jdir * sNqf[lf] + s] : 0.0;
                 else v = P.dt * qpe[sFbase[lf] + (int64_t)(25 * c + 20 + cp) * sNqf[lf] + s];
             }
             sFB[t] = v;
         }
         __syncthreads();
+        double *Er = E + (int64_t)r * Np * ld;
         for (int t = tid; t < Np * f; t += blockDim.x) {
             const int i = t / f, col = t % f;
             int lf = 0;
@@ -503,75 +553,101 @@ __global__ void __launch_bounds__(256) k_assemble_rows(DevMesh dm, Phys P, int e
             const int cp = (col - toff[lf]) / Nfp, b = (col - toff[lf]) % Nfp;
             double v = 0.0;
             int a0, a1;
-            if (on_face(i, p1, lf, a0, a1) && (!qrow || cp == c)) {
+            if ((!qrows || cp == c) && on_face_ix(i, lf, a0, a1)) {
                 const double *cf = sFB + (lf * 5 + cp) * 36;
                 for (int s = 0; s < sNqf[lf]; ++s) v += cf[s] * phi_face(lf, a0, a1, s) * mu_face(lf, b, s);
             }
             Er[(int64_t)i * ld + n + col] = v;
         }
-        // ---- residual column and padding
         for (int i = tid; i < Np; i += blockDim.x) {
             double v = 0.0;
             const double *rc = qpe + (int64_t)kVJac * Nq + (int64_t)(4 * r) * Nq;
+            const int ci = s_ix[i];
             for (int g = 0; g < Nq; ++g) {
-                double ph[4];
-                R.phi_all(i, g, ph);
-                v += rc[g] * ph[0] + rc[Nq + g] * ph[1] + rc[2 * Nq + g] * ph[2] + rc[3 * Nq + g] * ph[3];
+                const int cg = s_gx[g];
+                const int a0 = (ci & 15) * nq + (cg & 15), a1 = ((ci >> 4) & 15) * nq + ((cg >> 4) & 15),
+                          a2 = (ci >> 8) * nq + (cg >> 8);
+                const double l0 = sL[a0], l1 = sL[a1], l2 = sL[a2];
+                v += rc[g] * l0 * l1 * l2 + rc[Nq + g] * sD[a0] * l1 * l2 + rc[2 * Nq + g] * l0 * sD[a1] * l2 +
+                     rc[3 * Nq + g] * l0 * l1 * sD[a2];
             }
             for (int lf = 0; lf < 6; ++lf) {
                 int a0, a1;
-                if (!on_face(i, p1, lf, a0, a1)) continue;
+                if (!on_face_ix(i, lf, a0, a1)) continue;
                 const int Nqf = sNqf[lf];
                 const double *fb = qpe + sFbase[lf];
                 const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
                 for (int s = 0; s < Nqf; ++s) {
                     const double ph = phi_face(lf, a0, a1, s);
-                    if (qrow) v -= fgl[j * Nqf + s] * fb[(135 + c) * Nqf + s] * ph;
+                    if (qrows) v -= fgl[jdir * Nqf + s] * fb[(135 + c) * Nqf + s] * ph;
                     else v += P.dt * fb[(125 + c) * Nqf + s] * ph;
                 }
             }
             Er[(int64_t)i * ld + n + f] = v;
             for (int64_t col = n + f + 1; col < ld; ++col) Er[(int64_t)i * ld + col] = 0.0;
         }
-    } else {
-        // ================= trace rows of local face lf
-        const int lf = rb - 20;
-        const int pf1 = sPf[lf] + 1, Nfp = pf1 * pf1, Nqf = sNqf[lf];
-        const int F = dm.elem_face[6 * e + lf], bc = dm.face_bc[F];
-        const double *fb = qpe + sFbase[lf];
-        const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
-        double *Et = E + (int64_t)(n + toff[lf]) * ld;
-        const int nrow = 5 * Nfp;
-        for (int t = tid; t < nrow * (int)ld; t += blockDim.x) {
-            const int row = t / (int)ld, col = t % (int)ld;
-            const int c = row / Nfp, a = row % Nfp;
-            double v = 0.0;
-            if (col < n) {
-                const int sblk = col / Np, k = col % Np;
-                int ka0, ka1;
-                if (!bc && on_face(k, p1, lf, ka0, ka1)) {
-                    const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
-                    const double *cf = fb + (int64_t)(25 * c + slot) * Nqf;
-                    for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * phi_face(lf, ka0, ka1, s);
-                }
-            } else if (col < n + f) {
-                const int cc = col - n;
-                if (cc >= toff[lf] && cc < toff[lf + 1]) {
-                    const int cp = (cc - toff[lf]) / Nfp, b = (cc - toff[lf]) % Nfp;
-                    if (bc) {
-                        if (cp == c)
-                            for (int s = 0; s < Nqf; ++s) v += fgl[3 * Nqf + s] * mu_face(lf, a, s) * mu_face(lf, b, s);
-                    } else {
-                        const double *cf = fb + (int64_t)(25 * c + 20 + cp) * Nqf;
-                        for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * mu_face(lf, b, s);
-                    }
-                }
-            } else if (col == n + f) {
-                const double *cf = fb + (int64_t)((bc ? 130 : 125) + c) * Nqf;
-                for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s);
+    }
+}
+
+// Trace rows of local face lf: [C | D | R_uh] rows of this element's side.
+__global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
+                                                             double *__restrict__ Ebase) {
+    const int e = e0 + blockIdx.y, lf = blockIdx.x;
+    const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
+    const int *toff = dm.toff + 7 * e;
+    const int n = 20 * Np, f = toff[6];
+    const int64_t ld = e_ld(n, f);
+    double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    const double *qpe = qp + (dm.qp_off[e] - dm.qp_off[e0]);
+    const int tid = threadIdx.x;
+    __shared__ double sLf[6][30], sMf[6][30];
+    __shared__ int sPf[6], sNqf[6];
+    __shared__ int64_t sFbase[6];
+    load_face_tables(dm, e, p, Nq, sLf, sMf, sPf, sNqf, sFbase);
+    __syncthreads();
+    auto phi_face = [&](int l, int a0, int a1, int s) {
+        const int nqf1 = sPf[l] + 2;
+        return sLf[l][a0 * nqf1 + (s % nqf1)] * sLf[l][a1 * nqf1 + (s / nqf1)];
+    };
+    auto mu_face = [&](int l, int b, int s) {
+        const int pf1 = sPf[l] + 1, nqf1 = sPf[l] + 2;
+        return sMf[l][(b % pf1) * nqf1 + (s % nqf1)] * sMf[l][(b / pf1) * nqf1 + (s / nqf1)];
+    };
+    const int pf1 = sPf[lf] + 1, Nfp = pf1 * pf1, Nqf = sNqf[lf];
+    const int F = dm.elem_face[6 * e + lf], bc = dm.face_bc[F];
+    const double *fb = qpe + sFbase[lf];
+    const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
+    double *Et = E + (int64_t)(n + toff[lf]) * ld;
+    const int nrow = 5 * Nfp;
+    for (int t = tid; t < nrow * (int)ld; t += blockDim.x) {
+        const int row = t / (int)ld, col = t % (int)ld;
+        const int c = row / Nfp, a = row % Nfp;
+        double v = 0.0;
+        if (col < n) {
+            const int sblk = col / Np, k = col % Np;
+            int ka0, ka1;
+            if (!bc && on_face(k, p1, lf, ka0, ka1)) {
+                const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
+                const double *cf = fb + (int64_t)(25 * c + slot) * Nqf;
+                for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * phi_face(lf, ka0, ka1, s);
             }
-            Et[(int64_t)row * ld + col] = v;
+        } else if (col < n + f) {
+            const int cc = col - n;
+            if (cc >= toff[lf] && cc < toff[lf + 1]) {
+                const int cp = (cc - toff[lf]) / Nfp, b = (cc - toff[lf]) % Nfp;
+                if (bc) {
+                    if (cp == c)
+                        for (int s = 0; s < Nqf; ++s) v += fgl[3 * Nqf + s] * mu_face(lf, a, s) * mu_face(lf, b, s);
+                } else {
+                    const double *cf = fb + (int64_t)(25 * c + 20 + cp) * Nqf;
+                    for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * mu_face(lf, b, s);
+                }
+            }
+        } else if (col == n + f) {
+            const double *cf = fb + (int64_t)((bc ? 130 : 125) + c) * Nqf;
+            for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s);
         }
+        Et[(int64_t)row * ld + col] = v;
     }
 }
 
@@ -588,11 +664,12 @@ int launch_element_system(const hdg_ctx *ctx, int e0, int ne, const double *Q, c
     for (int e = e0; e < e0 + ne; ++e) maxp = std::max(maxp, ctx->elem_p[e]);
     const double *qpc = qp;
     switch (maxp) {
-        case 1: hipLaunchKernelGGL(k_assemble_rows<1>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
-        case 2: hipLaunchKernelGGL(k_assemble_rows<2>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
-        case 3: hipLaunchKernelGGL(k_assemble_rows<4>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
-        default: hipLaunchKernelGGL(k_assemble_rows<8>, dim3(26, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+        case 1: hipLaunchKernelGGL(k_assemble_interior<1>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+        case 2: hipLaunchKernelGGL(k_assemble_interior<2>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+        case 3: hipLaunchKernelGGL(k_assemble_interior<4>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
+        default: hipLaunchKernelGGL(k_assemble_interior<8>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
     }
+    hipLaunchKernelGGL(k_assemble_trace_rows, dim3(6, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
     return (int)hipGetLastError();
 }
 

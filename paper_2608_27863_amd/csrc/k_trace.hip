@@ -113,30 +113,35 @@ __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__rest
 }
 
 // ------------------------------------------------------------- Schwarz setup
-// Systems [[S_r, I], [I, 0]] (row-major, row stride e_ld(f, f)).
+// Systems [[S_r', I], [I, 0]] (row-major, row stride e_ld(m, m)), m = f rounded up to
+// even; for odd f, S_r' = [[S_r, 0], [0, 1]] (one decoupled unknown).
 __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__restrict__ S, double *__restrict__ sys) {
     const int e = blockIdx.y;
     const int *to = dm.toff + 7 * e;
-    const int f = to[6];
-    const int64_t ld = e_ld(f, f);
+    const int f = to[6], m = f + (f & 1);
+    const int64_t ld = e_ld(m, m);
     double *base = sys + dm.asmsys_off[e];
-    const int64_t total = (int64_t)2 * f * ld;
+    const int64_t total = (int64_t)2 * m * ld;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(t / ld), c = (int)(t % ld);
         double v = 0.0;
-        if (r < f) {
-            if (c < f) {
-                int a = 0, b = 0;
-                while (r >= to[a + 1]) ++a;
-                while (c >= to[b + 1]) ++b;
-                const int k = dm.asm_blk[36 * e + 6 * a + b];
-                const int bF = to[a + 1] - to[a];
-                v = S[dm.bsr_val_off[k] + (r - to[a]) + (int64_t)(c - to[b]) * bF];
-            } else if (c < 2 * f) {
-                v = (c - f == r) ? 1.0 : 0.0;
+        if (r < m) {
+            if (c < m) {
+                if (r < f && c < f) {
+                    int a = 0, b = 0;
+                    while (r >= to[a + 1]) ++a;
+                    while (c >= to[b + 1]) ++b;
+                    const int k = dm.asm_blk[36 * e + 6 * a + b];
+                    const int bF = to[a + 1] - to[a];
+                    v = S[dm.bsr_val_off[k] + (r - to[a]) + (int64_t)(c - to[b]) * bF];
+                } else {
+                    v = (r == c) ? 1.0 : 0.0;
+                }
+            } else if (c < 2 * m) {
+                v = (c - m == r) ? 1.0 : 0.0;
             }
-        } else if (c < f) {
-            v = (c == r - f) ? 1.0 : 0.0;
+        } else if (c < m) {
+            v = (c == r - m) ? 1.0 : 0.0;
         }
         base[t] = v;
     }
@@ -146,8 +151,8 @@ __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__r
 template <typename T>
 __global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const double *__restrict__ sys, T *__restrict__ Sinv) {
     const int e = blockIdx.z;
-    const int f = dm.toff[7 * e + 6];
-    const int64_t ld = e_ld(f, f);
+    const int f = dm.toff[7 * e + 6], m = f + (f & 1);
+    const int64_t ld = e_ld(m, m);
     const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
     if (i0 >= f || j0 >= f) return;
     const double *base = sys + dm.asmsys_off[e];
@@ -156,7 +161,7 @@ __global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const double *_
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = i0 + r, j = j0 + tx;
-        tile[r][tx] = (i < f && j < f) ? -base[(int64_t)(f + i) * ld + f + j] : 0.0;
+        tile[r][tx] = (i < f && j < f) ? -base[(int64_t)(m + i) * ld + m + j] : 0.0;
     }
     __syncthreads();
     for (int c = ty; c < 32; c += 8) {
@@ -235,14 +240,22 @@ __global__ void __launch_bounds__(256) k_dot_partial(const double *__restrict__ 
     }
 }
 
-// out[v] = (accumulate ? out[v] : 0) + sum_b partial[b * stride + v]
-__global__ void k_dot_final(const double *__restrict__ partial, int nblk, int stride, int nv, double *__restrict__ out,
-                            int accumulate) {
-    const int v = threadIdx.x + blockIdx.x * blockDim.x;
+// out[v] = (accumulate ? out[v] : 0) + sum_b partial[b * stride + v]; one block per v,
+// fixed-shape tree (deterministic)
+__global__ void __launch_bounds__(256) k_dot_final(const double *__restrict__ partial, int nblk, int stride, int nv,
+                                                   double *__restrict__ out, int accumulate) {
+    const int v = blockIdx.x;
     if (v >= nv) return;
+    __shared__ double red[256];
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[b * stride + v];
-    out[v] = accumulate ? out[v] + s : s;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[b * stride + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = accumulate ? out[v] + red[0] : red[0];
 }
 
 // w -= sum_v coef[v] V[v]
@@ -485,7 +498,7 @@ int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv
     if ((err = launch_asm_apply(ctx, prec, Sinv, g, w, zloc, s))) return err;
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)w, 1, (int64_t)0,
                        (const double *)w, N, partial, stride);
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, (const double *)partial, kDotBlocks, stride, 1, scal, 0);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, (const double *)partial, kDotBlocks, stride, 1, scal, 0);
     hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, s, (const double *)scal, gam, hist, m);
     hipLaunchKernelGGL(k_scale_inv, dim3(gN), dim3(256), 0, s, (const double *)w, (const double *)scal, V, N);
     for (int j = 0; j < m; ++j) {
@@ -497,17 +510,17 @@ int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv
         for (int pass = 0; pass < 2; ++pass) {
             hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)V, j + 1, N,
                                (const double *)w, N, partial, stride);
-            hipLaunchKernelGGL(k_dot_final, dim3((j + 1 + 63) / 64), dim3(64), 0, s, (const double *)partial,
+            hipLaunchKernelGGL(k_dot_final, dim3(j + 1), dim3(256), 0, s, (const double *)partial,
                                kDotBlocks, stride, j + 1, pass == 0 ? hj : hcol, 0);
             hipLaunchKernelGGL(k_sub_multi, dim3(gN), dim3(256), 0, s, (const double *)V, j + 1, N,
                                (const double *)(pass == 0 ? hj : hcol), w, N);
             if (pass == 1)
-                hipLaunchKernelGGL(k_dot_final, dim3((j + 1 + 63) / 64), dim3(64), 0, s, (const double *)partial,
+                hipLaunchKernelGGL(k_dot_final, dim3(j + 1), dim3(256), 0, s, (const double *)partial,
                                    kDotBlocks, stride, j + 1, hj, 1);
         }
         hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)w, 1, (int64_t)0,
                            (const double *)w, N, partial, stride);
-        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, (const double *)partial, kDotBlocks, stride, 1, scal, 0);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, (const double *)partial, kDotBlocks, stride, 1, scal, 0);
         hipLaunchKernelGGL(k_scale_inv, dim3(gN), dim3(256), 0, s, (const double *)w, (const double *)scal,
                            V + (int64_t)(j + 1) * N, N);
         hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, H, m, j, (const double *)scal, cs, sn, gam, hist);
