@@ -10,7 +10,7 @@
 //
 // Two-level blocking, all elements of a chunk advancing together.  Per block
 // of kNBO = 128 pivot columns (two panels of kNB = 64):
-//   k_panel      one workgroup per element factors a 64-column panel (16-column
+//   k_panel      one workgroup per element factors a 64-column panel (8-column
 //                sub-panels held in registers), records its pivots, the net row
 //                permutation and L11^{-1}
 //   k_rowperm    applies a recorded permutation to a range of columns and forms
@@ -37,8 +37,9 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 
 constexpr int kNB = 64;       // panel width
 constexpr int kNBO = 128;     // pivot columns per trailing update
-constexpr int kW = 16;        // register sub-panel width
+constexpr int kW = 8;         // register sub-panel width
 constexpr int kPT = 512;      // panel kernel threads
+static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptions");
 // A recorded permutation of w swaps (row base+jj <-> piv[jj]): [0] = number of
 // displaced rows, [1 .. W] source row of each top row, then (dst, src) pairs.
 constexpr int kPerm64 = 1 + kNB + 2 * kNB;
@@ -81,36 +82,52 @@ __device__ inline void argmax_combine(double &v, int &r, double v2, int r2) {
     if (v2 > v || (v2 == v && r2 < r)) { v = v2; r = r2; }
 }
 
-// Compute the net row permutation of a sequence of swaps (row base+jj <-> piv[jj]).
-// Produces for each top row its source row, and (dst, src) for rows outside the top block.
-__device__ void build_perm(int base, int w, const int *piv, int *top_src, int *ndisp, int *disp, int *rows,
-                           int *cont) {  // rows, cont: scratch of 2w entries
-    int cnt = 0;
-    for (int jj = 0; jj < w; ++jj) { rows[cnt] = base + jj; cont[cnt] = base + jj; ++cnt; }
-    for (int jj = 0; jj < w; ++jj) {
-        const int a = base + jj, b = piv[jj];
-        if (a == b) continue;
-        int ia = -1, ib = -1;
-        for (int t = 0; t < cnt; ++t) {
-            if (rows[t] == a) ia = t;
-            if (rows[t] == b) ib = t;
+// Net row permutation of the swaps (row base+t <-> row piv[t]), t = 0 .. w-1, applied
+// in order, with piv[t] >= base+t.  top_src[t] is the row whose content ends in row
+// base+t; disp holds (dst, src) for every row >= base+w that a swap touched, in the
+// order of its first swap, and *ndisp their count.  The content a displaced row ends
+// with is always an original top row (a top row is final once its own swap is done),
+// so the displaced copies never read a row that another copy writes.
+// Every thread of the block calls it (w <= 128, at least 128 threads); piv is in LDS;
+// the results are visible to the block after its next barrier.
+__device__ void block_net_perm(int base, int w, const int *piv, int *top_src, int *ndisp, int *disp,
+                               int *s_wcnt) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // undo the swaps from the last to the first to find where position x's content came from
+    auto source = [&](int x) {
+        for (int t = w - 1; t >= 0; --t) {
+            const int pt = piv[t];
+            x = (x == base + t) ? pt : ((x == pt) ? base + t : x);
         }
-        if (ib < 0) { rows[cnt] = b; cont[cnt] = b; ib = cnt++; }
-        const int tmp = cont[ia];
-        cont[ia] = cont[ib];
-        cont[ib] = tmp;
+        return x;
+    };
+    bool keep = false;
+    int y = 0, src = 0;
+    if (tid < w) {
+        top_src[tid] = source(base + tid);
+        y = piv[tid];
+        keep = y >= base + w;
+        for (int t = 0; keep && t < tid; ++t) keep = piv[t] != y;  // first swap of row y only
+        if (keep) {
+            src = source(y);
+            keep = src != y;
+        }
     }
-    for (int jj = 0; jj < w; ++jj) top_src[jj] = cont[jj];
-    int nd = 0;
-    for (int t = w; t < cnt; ++t)
-        if (cont[t] != rows[t]) { disp[2 * nd] = rows[t]; disp[2 * nd + 1] = cont[t]; ++nd; }
-    *ndisp = nd;
+    const unsigned long long bal = __ballot(keep);
+    if (lane == 0 && wave < 2) s_wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    if (keep) {
+        const int pos = (wave == 1 ? s_wcnt[0] : 0) + __popcll(bal & ((1ull << lane) - 1));
+        disp[2 * pos] = y;
+        disp[2 * pos + 1] = src;
+    }
+    if (tid == 0) *ndisp = s_wcnt[0] + s_wcnt[1];
 }
 
 // ------------------------------------------------------------------ panel
 // Factor the panel columns [k0, k0+nb) over the pivot rows [k0, n) (the trace
 // rows n.. get their multipliers from k_crows).  Rows are distributed over the
-// threads (row cb + tid + kPT i), 16 columns at a time held in registers.
+// threads (row cb + tid + kPT i), kW columns at a time held in registers.
 template <int R, int TAG>
 __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase,
                                                double *__restrict__ Ebase, double *__restrict__ wsd,
@@ -130,7 +147,7 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     __shared__ int s_top[kNB], s_disp[2 * kNB], s_nd;
     __shared__ double s_L[kW][kW];
     __shared__ double s_U[kW][kNB];
-    __shared__ int s_rows[2 * kNBO], s_cont[2 * kNBO];
+    __shared__ int s_piv2[kNBO], s_wcnt[2];
     __shared__ double s_T[kNB][kNB + 1], s_I[kNB][kNB + 1];
     int info_k = 0;
 
@@ -155,7 +172,7 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
         }
 #pragma unroll
         for (int jj = 0; jj < kW; ++jj) {
-            if (jj >= w) break;
+            if (jj < w) {  // uniform; keeps jj a compile-time register index
             const int k = cb + jj;
             // pivot: largest |a| over rows k..n-1 (smallest row index on ties); NaN wins
             double best = -1.0;
@@ -227,6 +244,7 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
                     for (int c = jj + 1; c < kW; ++c) a[i][c] -= l * prow[c];
                 }
             }
+            }
         }
         // write the factored sub-panel back; keep its L11 in LDS
 #pragma unroll
@@ -246,14 +264,14 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
 #pragma unroll
             for (int c = 0; c < kW; ++c) s_L[tid][c] = a[0][c];
         }
-        if (tid == 0) build_perm(cb, w, s_piv + j0, s_top, &s_nd, s_disp, s_rows, s_cont);
+        block_net_perm(cb, w, s_piv + j0, s_top, &s_nd, s_disp, s_wcnt);
         __syncthreads();
         // apply the sub-panel's row permutation to the other panel columns
         // (left: earlier sub-panels' L; right: not yet factored columns)
         const int nleft = j0, nright = nb - j0 - w, nother = nleft + nright;
         {
             const int nd = s_nd;
-            const int items = (w + nd) * nother;  // <= 32 * 48 < 4 * kPT
+            const int items = (w + nd) * nother;  // <= 2 kW (kNB - kW) < 4 kPT
             double vals[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -322,57 +340,104 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     // record pivots, the panel's net permutation, L11^{-1} and U11^{-1}
     int *wi = wsi + (int64_t)blockIdx.x * kWsInt;
     for (int t = tid; t < nb; t += kPT) wi[kWsPiv + slot * kNB + t] = s_piv[t];
-    if (tid == 0) {
+    {
         int *pm = wi + (slot == 0 ? kWsPerm0 : kWsPerm1);
-        int nd;
-        build_perm(k0, nb, s_piv, pm + 1, &nd, pm + 1 + kNB, s_rows, s_cont);
-        pm[0] = nd;
+        block_net_perm(k0, nb, s_piv, pm + 1, pm, pm + 1 + kNB, s_wcnt);
+    }
+    // second panel of a 128-column block: the net permutation of all its swaps
+    // (pivots of panel 0 come from the previous launch, those of panel 1 from LDS)
+    if (slot == 1) {
+        const int n0 = k0 - kbase, nbo = n0 + nb;
+        for (int t = tid; t < nbo; t += kPT) s_piv2[t] = (t < n0) ? wi[kWsPiv + t] : s_piv[t - n0];
+        __syncthreads();
+        int *pm = wi + kWsPerm128;
+        block_net_perm(kbase, nbo, s_piv2, pm + 1, pm, pm + 1 + kNBO, s_wcnt);
     }
     for (int t = tid; t < kNB * kNB; t += kPT) {
         const int r = t / kNB, c = t % kNB;
         s_T[r][c] = (r < nb && c < nb) ? E[(int64_t)(k0 + r) * ld + k0 + c] : 0.0;
+        s_I[r][c] = 0.0;
     }
     __syncthreads();
+    // Both inverses by 8 x 8 block substitution over the whole block: first the
+    // diagonal blocks (one thread per column), then one block row at a time,
+    // P = (off-diagonal part of the row) x (finished rows of the inverse) and
+    // X_row = -X_diag P.  Rows and columns >= nb act as identity and are
+    // returned as zero.
+    double (*s_P)[kNB] = s_U;  // [8][64] partial products
     if (tid < kNB) {
-        // column j of L11^{-1} (unit lower) by forward substitution
-        const int j = tid;
-        for (int r = 0; r < kNB; ++r) {
-            double x = (r == j) ? 1.0 : 0.0;
-            if (r > j)
-                for (int rr = j; rr < r; ++rr) x -= s_T[r][rr] * s_I[rr][j];
-            s_I[r][j] = (r < nb) ? x : 0.0;
+        // diagonal block of L11^{-1}: forward substitution, unit diagonal
+        const int j = tid, bi = j & ~7, jl = j & 7;
+        double x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            double v = (r == jl) ? 1.0 : 0.0;
+#pragma unroll
+            for (int c = 0; c < r; ++c) v -= s_T[bi + r][bi + c] * x[c];
+            x[r] = (r >= jl) ? v : 0.0;
+            s_I[bi + r][j] = x[r];
         }
     }
     __syncthreads();
+    for (int bI = 8; bI < kNB; bI += 8) {
+        const int i = tid & 7, j = tid >> 3;  // j < bI: columns left of the block row
+        if (j < bI) {
+            double v = 0.0;
+            for (int k = j & ~7; k < bI; ++k) v += s_T[bI + i][k] * s_I[k][j];
+            s_P[i][j] = v;
+        }
+        __syncthreads();
+        if (j < bI) {
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v -= s_I[bI + i][bI + c] * s_P[c][j];
+            s_I[bI + i][j] = v;
+        }
+        __syncthreads();
+    }
     double *li = wsd + (int64_t)blockIdx.x * kWsDbl + slot * kNB * kNB;
-    for (int t = tid; t < kNB * kNB; t += kPT) li[t] = s_I[t / kNB][t % kNB];
+    for (int t = tid; t < kNB * kNB; t += kPT) {
+        const int r = t / kNB, c = t % kNB;
+        li[t] = (r < nb && c < nb) ? s_I[r][c] : 0.0;
+    }
+    __syncthreads();
+    for (int t = tid; t < kNB * kNB; t += kPT) s_I[t / kNB][t % kNB] = 0.0;
     __syncthreads();
     if (tid < kNB) {
-        // column j of U11^{-1} by back substitution
-        const int j = tid;
-        for (int r = kNB - 1; r >= 0; --r) {
-            double x = 0.0;
-            if (r <= j && j < nb) {
-                x = (r == j) ? 1.0 : 0.0;
-                for (int c = r + 1; c <= j; ++c) x -= s_T[r][c] * s_I[c][j];
-                x /= s_T[r][r];
-            }
-            s_I[r][j] = x;
+        // diagonal block of U11^{-1}: back substitution
+        const int j = tid, bi = j & ~7, jl = j & 7;
+        double x[8];
+#pragma unroll
+        for (int r = 7; r >= 0; --r) {
+            double v = (r == jl) ? 1.0 : 0.0;
+#pragma unroll
+            for (int c = r + 1; c < 8; ++c) v -= s_T[bi + r][bi + c] * x[c];
+            const double d = (bi + r < nb) ? s_T[bi + r][bi + r] : 1.0;
+            x[r] = (r <= jl) ? v / d : 0.0;
+            s_I[bi + r][j] = x[r];
         }
     }
     __syncthreads();
+    for (int bI = kNB - 16; bI >= 0; bI -= 8) {
+        const int i = tid & 7, j = bI + 8 + (tid >> 3);  // columns right of the block row
+        if (j < kNB) {
+            double v = 0.0;
+            for (int k = bI + 8; k <= (j | 7); ++k) v += s_T[bI + i][k] * s_I[k][j];
+            s_P[i][j] = v;
+        }
+        __syncthreads();
+        if (j < kNB) {
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v -= s_I[bI + i][bI + c] * s_P[c][j];
+            s_I[bI + i][j] = v;
+        }
+        __syncthreads();
+    }
     double *ui = wsd + (int64_t)blockIdx.x * kWsDbl + (2 + slot) * kNB * kNB;
-    for (int t = tid; t < kNB * kNB; t += kPT) ui[t] = s_I[t / kNB][t % kNB];
-    // second panel of a 128-column block: the net permutation of all its swaps
-    if (slot == 1 && tid == 0) {
-        // pivots of panel 0 come from the previous launch, those of panel 1 from LDS
-        int *pm = wi + kWsPerm128;
-        const int n0 = k0 - kbase, nbo = n0 + nb;
-        for (int t = nb - 1; t >= 0; --t) s_piv[n0 + t] = s_piv[t];
-        for (int t = 0; t < n0; ++t) s_piv[t] = wi[kWsPiv + t];
-        int nd;
-        build_perm(kbase, nbo, s_piv, pm + 1, &nd, pm + 1 + kNBO, s_rows, s_cont);
-        pm[0] = nd;
+    for (int t = tid; t < kNB * kNB; t += kPT) {
+        const int r = t / kNB, c = t % kNB;
+        ui[t] = (r < nb && c < nb) ? s_I[r][c] : 0.0;
     }
     if (tid == 0 && info_k && info[e] == 0) info[e] = info_k;
 }
@@ -487,6 +552,11 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
         sX[r][c] = (c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : 0.0;
     }
     for (int t = tid; t < (kNBO - nrows) * 64; t += 256) sX[nrows + (t >> 6)][t & 63] = 0.0;
+    // a top row's source may be a displaced row: its old content must be read
+    // before the displaced copies overwrite it
+    __syncthreads();
+    // displaced rows take original top rows, which are rewritten only after the
+    // next barrier
     const int nd = sperm[0];
     for (int t = tid; t < nd * 64; t += 256) {
         const int d = t >> 6, c = t & 63;
@@ -495,7 +565,7 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
             E[(int64_t)dst * ld + c0 + c] = E[(int64_t)src * ld + c0 + c];
         }
     }
-    __syncthreads();
+    if (MODE == 1) __syncthreads();
     if (MODE != 1) {
         const double *la = wsd + (int64_t)blockIdx.y * kWsDbl;
         d4 acc[4];
