@@ -4,11 +4,14 @@ One step = one Newton step of the whole hot path on the 8^3 periodic
 supersonic Taylor-Green workload at p = 3 (512 hexahedra, n = 1280 interior and
 f = 480 trace unknowns per element): element residuals and Jacobians,
 condensation, trace assembly, additive-Schwarz set-up, 30 GMRES iterations and
-interior recovery, all inputs resident in HBM.
+interior recovery, all inputs resident in HBM.  The FP64 step is the headline
+figure; the mixed-precision step (FP32 factorisation, one FP64-residual
+refinement, FP64 Schur product, FP32 Schwarz inverses) is timed on the same
+workload beside it, with its differences from the FP64 step.
 
 Prints one JSON line: whole-step throughput in elements/s, the condensation
-roofline (FP64 MFMA), the face-matvec roofline (HBM), and the CPU oracle
-timed on a bounded sample of the same workload.
+roofline (FP64 matrix cores), the face-matvec roofline (HBM), the mixed step,
+and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -23,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 
 
@@ -30,6 +34,16 @@ def condense_flops_per_element(n, f):
     """Dense condensation as specified: LU of A (2n^3/3), solve with n x (f+1)
     right-hand sides (2n^2(f+1)), Schur product C X (2fn(f+1))."""
     return 2.0 * n ** 3 / 3.0 + 2.0 * n * n * (f + 1) + 2.0 * f * n * (f + 1)
+
+
+def mixed_flops_per_element(n, f, refine=1):
+    """Mixed condensation as specified, (FP32 flops, FP64 flops): FP32 LU
+    (2n^3/3), FP32 forward and back substitution of n x (f+1) right-hand sides
+    (2n^2(f+1)), per refinement step a dense FP64 residual (2n^2(f+1)) and an
+    FP32 solve (2n^2(f+1)); the FP64 Schur product (2fn(f+1))."""
+    f32 = 2.0 * n ** 3 / 3.0 + 2.0 * n * n * (f + 1) * (1 + refine)
+    f64 = 2.0 * n * n * (f + 1) * refine + 2.0 * f * n * (f + 1)
+    return f32, f64
 
 
 def matvec_bytes(ctx):
@@ -113,17 +127,54 @@ def main():
     if not np.all(st.info.cpu().numpy() == 0) or not np.all(st.asm_info.cpu().numpy() == 0):
         raise RuntimeError("zero pivot reported during the warm-up")
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
-    phase_ms = {ph: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
-                for i, ph in enumerate(phases)}
+    def timed(run_step):
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            run_step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phase_ms = {ph: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
+                    for i, ph in enumerate(phases)}
+        return 1e3 * wall / args.steps, phase_ms
+
+    ms_step, phase_ms = timed(step)
     print(f"[bench] {args.steps} timed steps: {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
+    S64, g64, d64 = st.S.clone(), st.g.clone(), st.dUhat.clone()
+
+    # mixed-precision step on the same workload and context
+    stm = pipeline.NewtonStep(wl, prec=hdg.HDG_MIXED, refine_steps=1, ctx=ctx)
+
+    def step_mixed(events=None):
+        for i, ph in enumerate(phases):
+            if events is not None:
+                events[i].record(stream)
+            getattr(stm, ph)()
+        if events is not None:
+            events[-1].record(stream)
+
+    for w in range(args.warmup):
+        step_mixed()
+        torch.cuda.synchronize()
+    if not np.all(stm.info.cpu().numpy() == 0) or not np.all(stm.asm_info.cpu().numpy() == 0):
+        raise RuntimeError("zero pivot reported in the mixed warm-up")
+    ms_mixed, phase_mixed = timed(step_mixed)
+    print(f"[bench] mixed: {ms_mixed:.2f} ms/step", file=sys.stderr, flush=True)
+    relnorm = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    f32fl, f64fl = mixed_flops_per_element(n, f, 1)
+    t_cm = phase_mixed["condense"] * 1e-3
+    t_peak = ne * (f32fl / (PEAK_FP32_TFLOPS * 1e12) + f64fl / (PEAK_FP64_TFLOPS * 1e12))
+    mixed = {
+        "value": ne / (ms_mixed * 1e-3), "unit": "elements/s", "ms_per_step": ms_mixed,
+        "condense_elements_per_s": ne / t_cm, "phase_ms": phase_mixed,
+        "refine_steps": 1, "schwarz": "element-block, FP32 inverses",
+        "rel_diff_vs_fp64_step": {"S": relnorm(stm.S, S64), "g": relnorm(stm.g, g64),
+                                  "dUhat_fixed_m": relnorm(stm.dUhat, d64)},
+        "roofline": {"bound": "mfma", "time_at_peak_ms": 1e3 * t_peak, "frac": t_peak / t_cm,
+                     "algorithmic": f"{f32fl:.4e} FP32 + {f64fl:.4e} FP64 flop/element x {ne} elements "
+                                    f"(peaks {PEAK_FP32_TFLOPS} / {PEAK_FP64_TFLOPS} TFLOP/s)"},
+    }
 
     # condensation roofline (FP64 MFMA): dense algorithmic flops / hdg_condense time
     fl = condense_flops_per_element(n, f) * ne
@@ -167,12 +218,14 @@ def main():
         "phase_ms": phase_ms,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "hdg_condense (k_panel, k_swap_trsm, k_update per 64-column panel; k_extract)",
+                     "kernel": "hdg_condense (per 128-column block: k_panel x2, k_crows, k_rowperm, "
+                               "k_update; then k_extract)",
                      "algorithmic": f"{condense_flops_per_element(n, f):.4e} flop/element x {ne} elements"},
         "roofline_matvec": {"bound": "hbm", "achieved": mv_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                             "frac": mv_gbps / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_matvec",
                             "ms": mv_ms, "algorithmic_bytes": mv_bytes},
     }
+    out["mixed"] = mixed
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

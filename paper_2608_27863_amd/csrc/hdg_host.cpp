@@ -264,6 +264,8 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
     ctx->qp_off.assign(ne + 1, 0);
     ctx->asmsys_off.assign(ne + 1, 0);
     ctx->tloc_off.assign(ne + 1, 0);
+    ctx->m32_off.assign(ne + 1, 0);
+    ctx->x_off.assign(ne + 1, 0);
     ctx->vgeo_off.assign(ne + 1, 0);
     ctx->fgeo_off.assign(6 * ne + 1, 0);
     ctx->toff.assign(7 * ne, 0);
@@ -298,6 +300,8 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
         const int fe = f + (f & 1);  // Schwarz system size rounded up to even
         ctx->asmsys_off[e + 1] = ctx->asmsys_off[e] + (int64_t)(2 * fe) * hdg::e_ld(fe, fe);
         ctx->tloc_off[e + 1] = ctx->tloc_off[e] + f;
+        ctx->m32_off[e + 1] = ctx->m32_off[e] + (int64_t)n * hdg::e_ld(n, f);
+        ctx->x_off[e + 1] = ctx->x_off[e] + (int64_t)n * hdg::x_ld(f);
     }
     for (int F = 0; F < nf; ++F) ctx->max_b = std::max(ctx->max_b, trace_size(ctx->face_p[F]));
     // ---- tables and geometry
@@ -425,6 +429,8 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
     UP(ctx->qp_off, qp_off);
     UP(ctx->asmsys_off, asmsys_off);
     UP(ctx->tloc_off, tloc_off);
+    UP(ctx->m32_off, m32_off);
+    UP(ctx->x_off, x_off);
     UP(ctx->vgeo_off, vgeo_off);
     UP(ctx->fgeo_off, fgeo_off);
     UP(vgeo, vgeo);

@@ -52,6 +52,8 @@ struct DevMesh {
     const int64_t *qp_off;     // [n_elem+1]
     const int64_t *asmsys_off; // [n_elem+1] Schwarz inversion systems (2f x ld doubles)
     const int64_t *tloc_off;   // [n_elem+1] prefix sums of f_e (element-local trace vectors)
+    const int64_t *m32_off;    // [n_elem+1] FP32 interior systems [A | B R_qu] (n x e_ld floats)
+    const int64_t *x_off;      // [n_elem+1] X = A^{-1}[B | R_qu] (n x x_ld doubles)
     const int64_t *vgeo_off;   // [n_elem+1]  volume geometry: [10][Nq] = W, G00..G22 (G = J^{-1})
     const int64_t *fgeo_off;   // [n_elem*6+1] face geometry: [4][Nqf] = w N_x, w N_y, w N_z, w |N|
     const double *vgeo;
@@ -75,6 +77,8 @@ struct Phys {
 
 // Element-system row stride (doubles): n + f + 1 rounded up to a multiple of 8.
 __host__ __device__ inline int64_t e_ld(int n, int f) { return ((int64_t)(n + f + 1) + 7) / 8 * 8; }
+// Row stride of X (doubles): f + 1 rounded up to a multiple of 8.
+__host__ __device__ inline int64_t x_ld(int f) { return ((int64_t)(f + 1) + 7) / 8 * 8; }
 
 }  // namespace hdg
 
@@ -87,7 +91,7 @@ struct hdg_ctx {
     bool repeated_face = false;  // some element meets the same face twice
     std::vector<int> elem_p, face_p, elem_face, face_elem, face_bc, toff, elem_n, elem_f;
     std::vector<int64_t> node_off, face_off, E_off, SK_off, asm_off, qp_off, vgeo_off, fgeo_off, asmsys_off,
-        tloc_off;
+        tloc_off, m32_off, x_off;
     std::vector<int64_t> bsr_row_ptr64, bsr_col64, bsr_val_off;
     std::vector<int> bsr_row_ptr, bsr_col;
     hdg::DevMesh dm{};

@@ -1,22 +1,31 @@
 // Static condensation of the element systems (eqs. local-elimination,
-// schur-trace), FP64.
+// schur-trace), in FP64 and in mixed precision.
 //
-// E^K = [[A B R_qu],[C D R_uh]] (row-major) is reduced by a right-looking
+// FP64.  E^K = [[A B R_qu],[C D R_uh]] (row-major) is reduced by a right-looking
 // blocked LU with partial pivoting over the first n columns, pivots taken
 // among the interior rows 0..n-1 only, the elimination carried through the
 // trace rows and the right-hand columns.  After the n pivots the trailing
 // block is D - C A^{-1} B (= S^K) next to R_uh - C A^{-1} R_qu (= -g^K), and
 // rows 0..n-1 hold U and L^{-1} P [B | R_qu] for the recovery.
 //
+// Mixed.  The interior rows [A | B R_qu] are copied to FP32 and factorised by
+// the same blocked LU in FP32 (FP32 matrix cores, FP32 accumulation); a blocked
+// back substitution gives X_0 = A^{-1}[B | R_qu] in FP32.  Each refinement step
+// forms R = [B | R_qu] - A X in FP64 from the untouched FP64 system, solves
+// A d = R with the FP32 factors and adds d to X in FP64.  Finally
+// [S^K | -g^K] = [D | R_uh] - C X is formed with FP64 matrix cores and X is
+// stored in place of [B | R_qu] for the recovery.
+//
 // Two-level blocking, all elements of a chunk advancing together.  Per block
 // of kNBO = 128 pivot columns (two panels of kNB = 64):
 //   k_panel      one workgroup per element factors a 64-column panel (8-column
 //                sub-panels held in registers), records its pivots, the net row
-//                permutation and L11^{-1}
+//                permutation, L11^{-1} and U11^{-1}
+//   k_crows      multipliers of the trace rows, L_C = C_panel U11^{-1}
 //   k_rowperm    applies a recorded permutation to a range of columns and forms
-//                U12 = L11^{-1} P A12 with FP64 MFMA (for the 128-row block:
+//                U12 = L11^{-1} P A12 with matrix cores (for the 128-row block:
 //                U_a = La^{-1} X_a, X_b -= L_ba U_a, U_b = Lb^{-1} X_b)
-//   k_update     A22 -= L21 U12 with FP64 MFMA (16x16x4): first over the second
+//   k_update     A22 -= L21 U12 on matrix cores (16x16x4): first over the second
 //                panel's columns (K = 64), then over every trailing column with
 //                K = 128, which halves the trailing-matrix traffic of a 64-wide
 //                right-looking update; 128x128 tiles, the tiles of one element
@@ -32,8 +41,30 @@
 namespace hdg {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef double v2d __attribute__((ext_vector_type(2)));
+// Matrix-core tile of 16x16 outputs with k = 4 per instruction, FP64 or FP32.
+// Inputs: lane l holds A[l%16][l/16] and B[l/16][l%16]; output slot j of lane l
+// holds row rowof(l, j), column l%16.
+template <typename T> struct MF;
+template <> struct MF<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    typedef double v16 __attribute__((ext_vector_type(2)));  // one 16-byte access
+    static constexpr int V = 2;
+    __device__ static acc_t mfma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int rowof(int lane, int j) { return 4 * j + (lane >> 4); }
+};
+template <> struct MF<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    typedef float v16 __attribute__((ext_vector_type(4)));
+    static constexpr int V = 4;
+    __device__ static acc_t mfma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int rowof(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
 
 constexpr int kNB = 64;       // panel width
 constexpr int kNBO = 128;     // pivot columns per trailing update
@@ -44,25 +75,35 @@ static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptio
 // displaced rows, [1 .. W] source row of each top row, then (dst, src) pairs.
 constexpr int kPerm64 = 1 + kNB + 2 * kNB;
 constexpr int kPerm128 = 1 + kNBO + 2 * kNBO;
-// Per-element workspace: doubles [4][64*64] (L^{-1}, U^{-1} of the two panels), then
-// ints: piv[128] | perm of panel 0 | perm of panel 1 | perm of the 128 block.
-constexpr int kWsDbl = 4 * kNB * kNB;  // L^{-1} of panels 0, 1, then U^{-1} of panels 0, 1
+// Workspace of one element and one 128-column block: values [4][64*64] (L^{-1}
+// of panels 0, 1, then U^{-1} of panels 0, 1), then ints: piv[128] | perm of
+// panel 0 | perm of panel 1 | perm of the 128 block.  The FP64 path reuses one
+// block's worth per element; the mixed path keeps every block (its solves replay them).
+constexpr int kWsDbl = 4 * kNB * kNB;
 constexpr int kWsPiv = 0, kWsPerm0 = kNBO, kWsPerm1 = kWsPerm0 + kPerm64, kWsPerm128 = kWsPerm1 + kPerm64;
 constexpr int kWsInt = kWsPerm128 + kPerm128;
 
+template <typename T> struct WS {
+    T *d;        // element 0's values of the current block
+    int *i;      // element 0's ints of the current block
+    int64_t ds;  // per-element stride of d (values)
+    int64_t is;  // per-element stride of i (ints)
+};
+
 struct ElemDims {
-    int n, f, mrows;  // mrows = n + f
+    int n, f, mrows, ncols;  // pivot columns, trace size, rows, columns
     int64_t ld;
 };
-// Bordered systems factored here: mode 0 = element systems (n = 20 N_p, f = f_e),
-// mode 1 = Schwarz inversion systems [[S_r, I], [I, 0]] (n = f = f_r, rounded up to even).
+// Systems factored here: mode 0 = element systems (n = 20 N_p, f = f_e, all
+// n + f rows); mode 1 = Schwarz inversion systems [[S_r, I], [I, 0]] (n = f = f_r
+// rounded up to even); mode 2 = FP32 interior rows [A | B R_qu] (n rows).
 struct SysDesc {
     int mode;
-    const int64_t *off;  // [n_elem+1] offsets (doubles) of the systems
+    const int64_t *off;  // [n_elem+1] offsets (elements) of the systems
 };
 __device__ inline ElemDims elem_dims(const DevMesh &dm, const SysDesc &sd, int e) {
     ElemDims d;
-    if (sd.mode == 0) {
+    if (sd.mode != 1) {
         const int p = dm.elem_p[e];
         d.n = 20 * (p + 1) * (p + 1) * (p + 1);
         d.f = dm.toff[7 * e + 6];
@@ -73,12 +114,13 @@ __device__ inline ElemDims elem_dims(const DevMesh &dm, const SysDesc &sd, int e
         d.n = f + (f & 1);
         d.f = d.n;
     }
-    d.mrows = d.n + d.f;
+    d.mrows = (sd.mode == 2) ? d.n : d.n + d.f;
+    d.ncols = d.n + d.f + 1;
     d.ld = e_ld(d.n, d.f);
     return d;
 }
 
-__device__ inline void argmax_combine(double &v, int &r, double v2, int r2) {
+template <typename T> __device__ inline void argmax_combine(T &v, int &r, T v2, int r2) {
     if (v2 > v || (v2 == v && r2 < r)) { v = v2; r = r2; }
 }
 
@@ -128,46 +170,46 @@ __device__ void block_net_perm(int base, int w, const int *piv, int *top_src, in
 // Factor the panel columns [k0, k0+nb) over the pivot rows [k0, n) (the trace
 // rows n.. get their multipliers from k_crows).  Rows are distributed over the
 // threads (row cb + tid + kPT i), kW columns at a time held in registers.
-template <int R, int TAG>
+template <int R, int TAG, typename T>
 __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase,
-                                               double *__restrict__ Ebase, double *__restrict__ wsd,
-                                               int *__restrict__ wsi, int *__restrict__ info) {
+                                               T *__restrict__ Ebase, WS<T> ws, int *__restrict__ info) {
+    typedef typename MF<T>::v2 v2;
     const int e = e0 + blockIdx.x;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
     const int nb = min(kNB, dd.n - k0);
     const int n = dd.n;
-    double *E = Ebase + (sd.off[e] - sd.off[e0]);
+    T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ double s_val[kPT / 64];
+    __shared__ T s_val[kPT / 64];
     __shared__ int s_row[kPT / 64];
-    __shared__ double s_prow[kW], s_krow[kW];
+    __shared__ T s_prow[kW], s_krow[kW];
     __shared__ int s_piv[kNBO];
     __shared__ int s_top[kNB], s_disp[2 * kNB], s_nd;
-    __shared__ double s_L[kW][kW];
-    __shared__ double s_U[kW][kNB];
+    __shared__ T s_L[kW][kW];
+    __shared__ T s_U[kW][kNB];
     __shared__ int s_piv2[kNBO], s_wcnt[2];
-    __shared__ double s_T[kNB][kNB + 1], s_I[kNB][kNB + 1];
+    __shared__ T s_T[kNB][kNB + 1], s_I[kNB][kNB + 1];
     int info_k = 0;
 
     for (int j0 = 0; j0 < nb; j0 += kW) {
         const int w = min(kW, nb - j0), cb = k0 + j0;
-        double a[R][kW];
+        T a[R][kW];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int r = cb + tid + kPT * i;
-            const double *src = E + (int64_t)min(r, n - 1) * ld + cb;
+            const T *src = E + (int64_t)min(r, n - 1) * ld + cb;
             if (w == kW) {
 #pragma unroll
                 for (int c = 0; c < kW; c += 2) {
-                    const v2d v = *(const v2d *)(src + c);
-                    a[i][c] = (r < n) ? v.x : 0.0;
-                    a[i][c + 1] = (r < n) ? v.y : 0.0;
+                    const v2 v = *(const v2 *)(src + c);
+                    a[i][c] = (r < n) ? v.x : T(0);
+                    a[i][c + 1] = (r < n) ? v.y : T(0);
                 }
             } else {
 #pragma unroll
-                for (int c = 0; c < kW; ++c) a[i][c] = (r < n && c < w) ? src[c] : 0.0;
+                for (int c = 0; c < kW; ++c) a[i][c] = (r < n && c < w) ? src[c] : T(0);
             }
         }
 #pragma unroll
@@ -175,29 +217,29 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
             if (jj < w) {  // uniform; keeps jj a compile-time register index
             const int k = cb + jj;
             // pivot: largest |a| over rows k..n-1 (smallest row index on ties); NaN wins
-            double best = -1.0;
+            T best = T(-1);
             int brow = INT_MAX;
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = cb + tid + kPT * i;
                 if (r >= k && r < n) {
-                    double v = fabs(a[i][jj]);
-                    if (!(v == v)) v = INFINITY;
+                    T v = fabs(a[i][jj]);
+                    if (!(v == v)) v = T(INFINITY);
                     argmax_combine(best, brow, v, r);
                 }
             }
             for (int off = 32; off > 0; off >>= 1) {
-                const double v2 = __shfl_xor(best, off);
+                const T v2_ = __shfl_xor(best, off);
                 const int r2 = __shfl_xor(brow, off);
-                argmax_combine(best, brow, v2, r2);
+                argmax_combine(best, brow, v2_, r2);
             }
             if (lane == 0) { s_val[wave] = best; s_row[wave] = brow; }
             __syncthreads();
-            double bv = s_val[0];
+            T bv = s_val[0];
             int pr = s_row[0];
 #pragma unroll
             for (int t = 1; t < kPT / 64; ++t) argmax_combine(bv, pr, s_val[t], s_row[t]);
-            const bool bad = !(bv > 0.0) || !(bv < INFINITY) || pr == INT_MAX;
+            const bool bad = !(bv > T(0)) || !(bv < T(INFINITY)) || pr == INT_MAX;
             if (bad) {
                 pr = k;
                 if (info_k == 0) info_k = k + 1;
@@ -230,15 +272,15 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
                             for (int c = 0; c < kW; ++c) a[i][c] = s_krow[c];
                 }
             }
-            const double pinv = bad ? 0.0 : 1.0 / s_prow[jj];
-            double prow[kW];
+            const T pinv = bad ? T(0) : T(1) / s_prow[jj];
+            T prow[kW];
 #pragma unroll
             for (int c = jj + 1; c < kW; ++c) prow[c] = s_prow[c];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = cb + tid + kPT * i;
                 if (r > k && r < n) {
-                    const double l = a[i][jj] * pinv;
+                    const T l = a[i][jj] * pinv;
                     a[i][jj] = l;
 #pragma unroll
                     for (int c = jj + 1; c < kW; ++c) a[i][c] -= l * prow[c];
@@ -250,10 +292,10 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int r = cb + tid + kPT * i;
-            double *dst = E + (int64_t)r * ld + cb;
+            T *dst = E + (int64_t)r * ld + cb;
             if (r < n && w == kW) {
 #pragma unroll
-                for (int c = 0; c < kW; c += 2) *(v2d *)(dst + c) = (v2d){a[i][c], a[i][c + 1]};
+                for (int c = 0; c < kW; c += 2) *(v2 *)(dst + c) = (v2){a[i][c], a[i][c + 1]};
             } else if (r < n) {
 #pragma unroll
                 for (int c = 0; c < kW; ++c)
@@ -272,11 +314,11 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
         {
             const int nd = s_nd;
             const int items = (w + nd) * nother;  // <= 2 kW (kNB - kW) < 4 kPT
-            double vals[4];
+            T vals[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int t = tid + q * kPT;
-                vals[q] = 0.0;
+                vals[q] = T(0);
                 if (t < items) {
                     const int ridx = t / nother, cidx = t % nother;
                     const int col = (cidx < nleft) ? k0 + cidx : cb + w + (cidx - nleft);
@@ -301,9 +343,9 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
             // U of the sub-panel rows in the right columns: unit lower solve
             for (int cidx = tid; cidx < nright; cidx += kPT) {
                 const int col = cb + w + cidx;
-                double x[kW];
+                T x[kW];
 #pragma unroll
-                for (int r = 0; r < kW; ++r) x[r] = (r < w) ? E[(int64_t)(cb + r) * ld + col] : 0.0;
+                for (int r = 0; r < kW; ++r) x[r] = (r < w) ? E[(int64_t)(cb + r) * ld + col] : T(0);
 #pragma unroll
                 for (int r = 0; r < kW; ++r)
 #pragma unroll
@@ -311,7 +353,7 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
 #pragma unroll
                 for (int r = 0; r < kW; ++r) {
                     if (r < w) E[(int64_t)(cb + r) * ld + col] = x[r];
-                    s_U[r][cidx] = (r < w) ? x[r] : 0.0;
+                    s_U[r][cidx] = (r < w) ? x[r] : T(0);
                 }
             }
             __syncthreads();
@@ -320,11 +362,11 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
             for (int i = 0; i < R; ++i) {
                 const int r = cb + tid + kPT * i;
                 if (r < cb + w || r >= n) continue;
-                double *row = E + (int64_t)r * ld + cb + w;
+                T *row = E + (int64_t)r * ld + cb + w;
                 for (int c8 = 0; c8 < nright; c8 += 8) {
-                    double v[8];
+                    T v[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = (c8 + q < nright) ? row[c8 + q] : 0.0;
+                    for (int q = 0; q < 8; ++q) v[q] = (c8 + q < nright) ? row[c8 + q] : T(0);
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
 #pragma unroll
@@ -338,7 +380,8 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
         }
     }
     // record pivots, the panel's net permutation, L11^{-1} and U11^{-1}
-    int *wi = wsi + (int64_t)blockIdx.x * kWsInt;
+    int *wi = ws.i + (int64_t)blockIdx.x * ws.is;
+    T *wd = ws.d + (int64_t)blockIdx.x * ws.ds;
     for (int t = tid; t < nb; t += kPT) wi[kWsPiv + slot * kNB + t] = s_piv[t];
     {
         int *pm = wi + (slot == 0 ? kWsPerm0 : kWsPerm1);
@@ -355,8 +398,8 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     }
     for (int t = tid; t < kNB * kNB; t += kPT) {
         const int r = t / kNB, c = t % kNB;
-        s_T[r][c] = (r < nb && c < nb) ? E[(int64_t)(k0 + r) * ld + k0 + c] : 0.0;
-        s_I[r][c] = 0.0;
+        s_T[r][c] = (r < nb && c < nb) ? E[(int64_t)(k0 + r) * ld + k0 + c] : T(0);
+        s_I[r][c] = T(0);
     }
     __syncthreads();
     // Both inverses by 8 x 8 block substitution over the whole block: first the
@@ -364,17 +407,17 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     // P = (off-diagonal part of the row) x (finished rows of the inverse) and
     // X_row = -X_diag P.  Rows and columns >= nb act as identity and are
     // returned as zero.
-    double (*s_P)[kNB] = s_U;  // [8][64] partial products
+    T (*s_P)[kNB] = s_U;  // [8][64] partial products
     if (tid < kNB) {
         // diagonal block of L11^{-1}: forward substitution, unit diagonal
         const int j = tid, bi = j & ~7, jl = j & 7;
-        double x[8];
+        T x[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            double v = (r == jl) ? 1.0 : 0.0;
+            T v = (r == jl) ? T(1) : T(0);
 #pragma unroll
             for (int c = 0; c < r; ++c) v -= s_T[bi + r][bi + c] * x[c];
-            x[r] = (r >= jl) ? v : 0.0;
+            x[r] = (r >= jl) ? v : T(0);
             s_I[bi + r][j] = x[r];
         }
     }
@@ -382,38 +425,38 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     for (int bI = 8; bI < kNB; bI += 8) {
         const int i = tid & 7, j = tid >> 3;  // j < bI: columns left of the block row
         if (j < bI) {
-            double v = 0.0;
+            T v = T(0);
             for (int k = j & ~7; k < bI; ++k) v += s_T[bI + i][k] * s_I[k][j];
             s_P[i][j] = v;
         }
         __syncthreads();
         if (j < bI) {
-            double v = 0.0;
+            T v = T(0);
 #pragma unroll
             for (int c = 0; c < 8; ++c) v -= s_I[bI + i][bI + c] * s_P[c][j];
             s_I[bI + i][j] = v;
         }
         __syncthreads();
     }
-    double *li = wsd + (int64_t)blockIdx.x * kWsDbl + slot * kNB * kNB;
+    T *li = wd + slot * kNB * kNB;
     for (int t = tid; t < kNB * kNB; t += kPT) {
         const int r = t / kNB, c = t % kNB;
-        li[t] = (r < nb && c < nb) ? s_I[r][c] : 0.0;
+        li[t] = (r < nb && c < nb) ? s_I[r][c] : T(0);
     }
     __syncthreads();
-    for (int t = tid; t < kNB * kNB; t += kPT) s_I[t / kNB][t % kNB] = 0.0;
+    for (int t = tid; t < kNB * kNB; t += kPT) s_I[t / kNB][t % kNB] = T(0);
     __syncthreads();
     if (tid < kNB) {
         // diagonal block of U11^{-1}: back substitution
         const int j = tid, bi = j & ~7, jl = j & 7;
-        double x[8];
+        T x[8];
 #pragma unroll
         for (int r = 7; r >= 0; --r) {
-            double v = (r == jl) ? 1.0 : 0.0;
+            T v = (r == jl) ? T(1) : T(0);
 #pragma unroll
             for (int c = r + 1; c < 8; ++c) v -= s_T[bi + r][bi + c] * x[c];
-            const double d = (bi + r < nb) ? s_T[bi + r][bi + r] : 1.0;
-            x[r] = (r <= jl) ? v / d : 0.0;
+            const T d = (bi + r < nb) ? s_T[bi + r][bi + r] : T(1);
+            x[r] = (r <= jl) ? v / d : T(0);
             s_I[bi + r][j] = x[r];
         }
     }
@@ -421,97 +464,92 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     for (int bI = kNB - 16; bI >= 0; bI -= 8) {
         const int i = tid & 7, j = bI + 8 + (tid >> 3);  // columns right of the block row
         if (j < kNB) {
-            double v = 0.0;
+            T v = T(0);
             for (int k = bI + 8; k <= (j | 7); ++k) v += s_T[bI + i][k] * s_I[k][j];
             s_P[i][j] = v;
         }
         __syncthreads();
         if (j < kNB) {
-            double v = 0.0;
+            T v = T(0);
 #pragma unroll
             for (int c = 0; c < 8; ++c) v -= s_I[bI + i][bI + c] * s_P[c][j];
             s_I[bI + i][j] = v;
         }
         __syncthreads();
     }
-    double *ui = wsd + (int64_t)blockIdx.x * kWsDbl + (2 + slot) * kNB * kNB;
+    T *ui = wd + (2 + slot) * kNB * kNB;
     for (int t = tid; t < kNB * kNB; t += kPT) {
         const int r = t / kNB, c = t % kNB;
-        ui[t] = (r < nb && c < nb) ? s_I[r][c] : 0.0;
+        ui[t] = (r < nb && c < nb) ? s_I[r][c] : T(0);
     }
     if (tid == 0 && info_k && info[e] == 0) info[e] = info_k;
 }
 
+// acc (rows 16 wave .. +15, 64 columns) = Ls (64x64) * X (64 x 64), both in LDS.
+template <typename T>
+__device__ inline void mfma_64x64(const T (*Ls)[kNB + 1], const T (*X)[65], typename MF<T>::acc_t acc[4], int lane,
+                                  int wave) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = (typename MF<T>::acc_t){T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+    for (int kk = 0; kk < kNB; kk += 4) {
+        const T a = Ls[16 * wave + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const T b = X[kk + (lane >> 4)][16 * j + (lane & 15)];
+            acc[j] = MF<T>::mfma(a, b, acc[j]);
+        }
+    }
+}
+
 // Multipliers of the trace rows n..n+f-1 in the panel columns [kp, kp+nb):
-// L_C = C_panel U11^{-1} (FP64 MFMA), one workgroup per 64 trace rows.
-template <int TAG>
+// L_C = C_panel U11^{-1} (matrix cores), one workgroup per 64 trace rows.
+template <int TAG, typename T>
 __global__ void __launch_bounds__(256) k_crows(DevMesh dm, SysDesc sd, int e0, int kp, int slot,
-                                               double *__restrict__ Ebase, const double *__restrict__ wsd) {
+                                               T *__restrict__ Ebase, WS<T> ws) {
+    typedef typename MF<T>::acc_t acc_t;
     const int e = e0 + blockIdx.y;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (kp >= dd.n) return;
     const int nb = min(kNB, dd.n - kp);
     const int r0 = dd.n + blockIdx.x * 64;
     if (r0 >= dd.mrows) return;
-    double *E = Ebase + (sd.off[e] - sd.off[e0]);
+    T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ double sX[64][65];
-    __shared__ double sU[kNB][kNB + 1];
-    const double *ui = wsd + (int64_t)blockIdx.y * kWsDbl + (2 + slot) * kNB * kNB;
+    __shared__ T sX[64][65];
+    __shared__ T sU[kNB][kNB + 1];
+    const T *ui = ws.d + (int64_t)blockIdx.y * ws.ds + (2 + slot) * kNB * kNB;
     for (int t = tid; t < kNB * kNB; t += 256) sU[t >> 6][t & 63] = ui[t];
     for (int t = tid; t < 64 * 64; t += 256) {
         const int r = t >> 6, c = t & 63;
-        sX[r][c] = (r0 + r < dd.mrows && c < nb) ? E[(int64_t)(r0 + r) * ld + kp + c] : 0.0;
+        sX[r][c] = (r0 + r < dd.mrows && c < nb) ? E[(int64_t)(r0 + r) * ld + kp + c] : T(0);
     }
     __syncthreads();
-    d4 acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int kk = 0; kk < kNB; kk += 4) {
-        const double av = sX[16 * wave + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double bv = sU[kk + (lane >> 4)][16 * j + (lane & 15)];
-            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
-        }
-    }
+    acc_t acc[4];
+    mfma_64x64<T>(sX, sU, acc, lane, wave);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = r0 + 16 * wave + 4 * q + (lane >> 4), c = 16 * j + (lane & 15);
+            const int r = r0 + 16 * wave + MF<T>::rowof(lane, q), c = 16 * j + (lane & 15);
             if (r < dd.mrows && c < nb) E[(int64_t)r * ld + kp + c] = acc[j][q];
         }
 }
 
 // ------------------------------------------------------- row permutation
-// MODE 0: rows base..base+63 <- permuted (panel `slot`), U = L^{-1} X, on
+// MODE 0: rows base..base+63 <- permuted (panel 0), U = L^{-1} X, on
 //         columns [k0 + K_e, k0 + min(CW, n_e - k0))  (CW = 0: to the end)
 // MODE 1: permutation of panel 1 only, on the columns of panel 0 (its L)
 // MODE 2: 128-row block: X = P A12 (net permutation of both panels),
-//         U_a = La^{-1} X_a, X_b -= L_ba U_a, U_b = Lb^{-1} X_b, on the trailing columns
+//         U_a = La^{-1} X_a, X_b -= L_ba U_a, U_b = Lb^{-1} X_b, on the trailing
+//         columns (rhs = 1: on the right-hand columns n.. only, which replays the
+//         block's forward substitution on a new right-hand side)
 // One workgroup per (64-column tile, element).
-__device__ inline void mfma_64x64(const double (*Ls)[kNB + 1], const double (*X)[65], d4 acc[4], int lane, int wave) {
-    // acc (rows 16 wave .. +15, 64 columns) = Ls (64x64) * X (64 x 64)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int kk = 0; kk < kNB; kk += 4) {
-        const double a = Ls[16 * wave + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double b = X[kk + (lane >> 4)][16 * j + (lane & 15)];
-            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
-        }
-    }
-}
-
-template <int MODE, int TAG>
-__global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0, int k0, int CW,
-                                                 double *__restrict__ Ebase, const double *__restrict__ wsd,
-                                                 const int *__restrict__ wsi) {
+template <int MODE, int TAG, typename T>
+__global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0, int k0, int CW, int rhs,
+                                                 T *__restrict__ Ebase, WS<T> ws) {
+    typedef typename MF<T>::acc_t acc_t;
     const int e = e0 + blockIdx.y;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
@@ -520,7 +558,7 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
     if (MODE == 0) {
         const int K = min(kNB, rem);
         c_begin = k0 + K;
-        c_end = CW > 0 ? k0 + min(CW, rem) : dd.mrows + 1;
+        c_end = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
         base = k0; nrows = K; permoff = kWsPerm0;
     } else if (MODE == 1) {
         if (rem <= kNB) return;
@@ -529,19 +567,19 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
         base = k0 + kNB; nrows = min(kNB, rem - kNB); permoff = kWsPerm1;
     } else {
         const int nbo = min(kNBO, rem);
-        c_begin = k0 + nbo;
-        c_end = dd.mrows + 1;
+        c_begin = rhs ? dd.n : k0 + nbo;
+        c_end = dd.ncols;
         base = k0; nrows = nbo; permoff = (nbo > kNB) ? kWsPerm128 : kWsPerm0;
     }
     const int c0 = c_begin + blockIdx.x * 64;
     if (c0 >= c_end) return;  // uniform per block
-    double *E = Ebase + (sd.off[e] - sd.off[e0]);
+    T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ double sX[kNBO][65];
-    __shared__ double sM[kNB][kNB + 1];
+    __shared__ T sX[kNBO][65];
+    __shared__ T sM[kNB][kNB + 1];
     __shared__ int sperm[kPerm128];
-    const int *wi = wsi + (int64_t)blockIdx.y * kWsInt;
+    const int *wi = ws.i + (int64_t)blockIdx.y * ws.is;
     const int W = (permoff == kWsPerm128) ? kNBO : kNB;
     const int permlen = 1 + W + 2 * W;
     for (int t = tid; t < permlen; t += 256) sperm[t] = wi[permoff + t];
@@ -549,9 +587,9 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
     // gather the permuted top rows, then move the displaced rows
     for (int t = tid; t < nrows * 64; t += 256) {
         const int r = t >> 6, c = t & 63;
-        sX[r][c] = (c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : 0.0;
+        sX[r][c] = (c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : T(0);
     }
-    for (int t = tid; t < (kNBO - nrows) * 64; t += 256) sX[nrows + (t >> 6)][t & 63] = 0.0;
+    for (int t = tid; t < (kNBO - nrows) * 64; t += 256) sX[nrows + (t >> 6)][t & 63] = T(0);
     // a top row's source may be a displaced row: its old content must be read
     // before the displaced copies overwrite it
     __syncthreads();
@@ -567,41 +605,43 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
     }
     if (MODE == 1) __syncthreads();
     if (MODE != 1) {
-        const double *la = wsd + (int64_t)blockIdx.y * kWsDbl;
-        d4 acc[4];
+        const T *la = ws.d + (int64_t)blockIdx.y * ws.ds;
+        acc_t acc[4];
         // U_a = La^{-1} X_a
         for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = la[t];
         __syncthreads();
-        mfma_64x64(sM, sX, acc, lane, wave);
+        mfma_64x64<T>(sM, sX, acc, lane, wave);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sX[16 * wave + 4 * q + (lane >> 4)][16 * j + (lane & 15)] = acc[j][q];
+            for (int q = 0; q < 4; ++q) sX[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
         if (nrows > kNB) {
             // X_b -= L_ba U_a   (L_ba: rows base+64.., columns base.. of E, already permuted)
             __syncthreads();
             for (int t = tid; t < kNB * kNB; t += 256) {
                 const int r = t >> 6, c = t & 63;
-                sM[r][c] = (kNB + r < nrows) ? E[(int64_t)(base + kNB + r) * ld + base + c] : 0.0;
+                sM[r][c] = (kNB + r < nrows) ? E[(int64_t)(base + kNB + r) * ld + base + c] : T(0);
             }
             __syncthreads();
-            mfma_64x64(sM, sX, acc, lane, wave);
+            mfma_64x64<T>(sM, sX, acc, lane, wave);
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) sX[kNB + 16 * wave + 4 * q + (lane >> 4)][16 * j + (lane & 15)] -= acc[j][q];
+                for (int q = 0; q < 4; ++q)
+                    sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] -= acc[j][q];
             // U_b = Lb^{-1} X_b
             __syncthreads();
             for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = la[kNB * kNB + t];
             __syncthreads();
-            mfma_64x64(sM, (const double (*)[65])(&sX[kNB][0]), acc, lane, wave);
+            mfma_64x64<T>(sM, (const T (*)[65])(&sX[kNB][0]), acc, lane, wave);
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) sX[kNB + 16 * wave + 4 * q + (lane >> 4)][16 * j + (lane & 15)] = acc[j][q];
+                for (int q = 0; q < 4; ++q)
+                    sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
         }
         __syncthreads();
     }
@@ -612,18 +652,33 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
 }
 
 // --------------------------------------------------------- trailing update
-// A22 -= L21 U12 with L21 = E[rows, k0 .. k0+K), U12 = E[k0 .. k0+K, cols],
-// K = min(KW, n_e - k0); rows [k0+K, n+f), columns [k0+K, k0+min(CW, n_e-k0))
-// (CW > 0) or [k0+K, n+f+1).  128 x 128 tile per workgroup, K in chunks of 16
-// double-buffered through LDS, FP64 MFMA into zero-initialised accumulators,
-// the subtraction from A22 in the epilogue.
-constexpr int kTM = 128, kTN = 128, kKC = 16;
-constexpr int kSA = kKC + 2;    // LDS row stride of the L21 chunk (rows x k)
-constexpr int kSB = kTN + 16;   // LDS row stride of the U12 chunk (k x columns)
+// C -= A B within one system, K = min(KW, n_e - k0) and A = E[rows, k0 .. k0+K),
+// B = E[k0 .. k0+K, cols]:
+//   kRangeLU:  rows [k0+K, mrows), columns [k0+K, k0+min(CW, n_e-k0)) (CW > 0) or
+//              [k0+K, ncols)  (the LU's trailing update)
+//   kRangeFwd: rows [k0+K, n), columns [n, ncols)  (forward substitution of the
+//              right-hand columns)
+//   kRangeBwd: rows [0, k0), columns [n, ncols)    (back substitution: U12 X2)
+// 128 x 128 tile per workgroup, K in chunks of 16 (FP64) or 32 (FP32) values
+// double-buffered through LDS, matrix cores into zero-initialised accumulators,
+// the subtraction in the epilogue.
+constexpr int kRangeLU = 0, kRangeFwd = 1, kRangeBwd = 2;
+constexpr int kTM = 128, kTN = 128;
+template <typename T> struct UpdCfg {
+    static constexpr int V = MF<T>::V;
+    static constexpr int KC = 8 * V;      // k per LDS chunk
+    static constexpr int SA = KC + V;     // LDS row stride of the A chunk (rows x k)
+    static constexpr int SB = kTN + 16;   // LDS row stride of the B chunk (k x columns)
+    static constexpr int LPK = kTN / V;   // lanes per k-row of the B chunk
+    static constexpr int KPQ = 256 / LPK; // k-rows of B per load step
+};
 
-template <int TAG>
+template <typename T, int TAG, int RANGE>
 __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int KW, int CW,
-                                                   int tiles_m, int tiles_n, double *__restrict__ Ebase) {
+                                                   int tiles_m, int tiles_n, T *__restrict__ Ebase) {
+    typedef UpdCfg<T> C;
+    typedef typename MF<T>::v16 v16;
+    typedef typename MF<T>::acc_t acc_t;
     // XCD-aware mapping: consecutive workgroups go round-robin over the 8 XCDs;
     // give each XCD a contiguous range of (element, tile) work items.
     const int total = ne * tiles_m * tiles_n;
@@ -636,25 +691,32 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     if (k0 >= dd.n) return;
     const int rem = dd.n - k0;
     const int K = min(KW, rem);
-    const int r0 = k0 + K + (t / tiles_n) * kTM;
-    const int c0 = k0 + K + (t % tiles_n) * kTN;
-    const int rend = dd.mrows;
-    const int cend = CW > 0 ? k0 + min(CW, rem) : dd.mrows + 1;
+    int rbeg, rend, cbeg, cend;
+    if (RANGE == kRangeLU) {
+        rbeg = k0 + K; rend = dd.mrows; cbeg = k0 + K; cend = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
+    } else if (RANGE == kRangeFwd) {
+        rbeg = k0 + K; rend = dd.n; cbeg = dd.n; cend = dd.ncols;
+    } else {
+        rbeg = 0; rend = k0; cbeg = dd.n; cend = dd.ncols;
+    }
+    const int r0 = rbeg + (t / tiles_n) * kTM;
+    const int c0 = cbeg + (t % tiles_n) * kTN;
     if (r0 >= rend || c0 >= cend) return;
-    double *E = Ebase + (sd.off[e] - sd.off[e0]);
+    T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;  // wave sub-tile origin
-    __shared__ double sA[2][kTM][kSA];
-    __shared__ double sB[2][kKC][kSB];
-    // chunk loads with 16-byte accesses: L21 chunk (128 rows x 16 k): 8 lanes per
-    // row segment of 128 bytes, rows 32q + tid/8; U12 chunk (16 k x 128 columns):
-    // one wave per k-row of 1 KB, k-rows 4q + tid/64.  Out-of-range entries are
+    __shared__ __attribute__((aligned(16))) T sA[2][kTM][C::SA];
+    __shared__ __attribute__((aligned(16))) T sB[2][C::KC][C::SB];
+    // chunk loads with 16-byte accesses: A chunk (128 rows x KC k): 8 lanes per
+    // 128-byte row segment, rows 32q + tid/8; B chunk (KC k x 128 columns): LPK
+    // lanes per k-row of 1 KB (FP64) or 512 B (FP32).  Out-of-range entries are
     // read from a clamped in-range address and replaced by 0 (no branches): K and
-    // every column offset are even, and a row holds ld >= n+f+1 entries.
-    const int ar = tid >> 3, ak = (tid & 7) * 2;
-    const int bk = tid >> 6, bc = (tid & 63) * 2;
-    const double *arow[4];
+    // every column offset are multiples of V, and a row holds ld >= ncols entries
+    // with ld a multiple of 8.
+    const int ar = tid >> 3, ak = (tid & 7) * C::V;
+    const int bk = tid / C::LPK, bc = (tid % C::LPK) * C::V;
+    const T *arow[4];
     bool aok[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -663,49 +725,48 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
         arow[q] = E + (int64_t)min(row, rend - 1) * ld + k0;
     }
     const int bcol = c0 + bc;
-    const bool bok0 = bcol < cend, bok1 = bcol + 1 < cend;
-    const int bcolc = min(bcol, (cend - 1) & ~1);
-    auto load_chunk = [&](int kc, v2d *ra, v2d *rb) {
+    const int bcolc = min(bcol, (cend - 1) & ~(C::V - 1));
+    auto load_chunk = [&](int kc, v16 *ra, v16 *rb) {
         const int gk = kc + ak;
-        const int gkc = min(gk, (K - 1) & ~1);
+        const int gkc = min(gk, (K - 1) & ~(C::V - 1));
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const v2d v = *(const v2d *)(arow[q] + gkc);
-            ra[q].x = (aok[q] && gk < K) ? v.x : 0.0;
-            ra[q].y = (aok[q] && gk + 1 < K) ? v.y : 0.0;
+            const v16 v = *(const v16 *)(arow[q] + gkc);
+#pragma unroll
+            for (int i = 0; i < C::V; ++i) ra[q][i] = (aok[q] && gk + i < K) ? v[i] : T(0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int gk2 = kc + 4 * q + bk;
+            const int gk2 = kc + C::KPQ * q + bk;
             const bool k2ok = gk2 < K;
-            const v2d v = *(const v2d *)(E + (int64_t)(k0 + min(gk2, K - 1)) * ld + bcolc);
-            rb[q].x = (k2ok && bok0) ? v.x : 0.0;
-            rb[q].y = (k2ok && bok1) ? v.y : 0.0;
+            const v16 v = *(const v16 *)(E + (int64_t)(k0 + min(gk2, K - 1)) * ld + bcolc);
+#pragma unroll
+            for (int i = 0; i < C::V; ++i) rb[q][i] = (k2ok && bcol + i < cend) ? v[i] : T(0);
         }
     };
-    auto store_chunk = [&](int buf, const v2d *ra, const v2d *rb) {
+    auto store_chunk = [&](int buf, const v16 *ra, const v16 *rb) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            *(v2d *)&sA[buf][32 * q + ar][ak] = ra[q];
-            *(v2d *)&sB[buf][4 * q + bk][bc] = rb[q];
+            *(v16 *)&sA[buf][32 * q + ar][ak] = ra[q];
+            *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = rb[q];
         }
     };
-    d4 acc[4][4];
+    acc_t acc[4][4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
-    v2d ra[4], rb[4];
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = (acc_t){T(0), T(0), T(0), T(0)};
+    v16 ra[4], rb[4];
     load_chunk(0, ra, rb);
     store_chunk(0, ra, rb);
     __syncthreads();
-    const int nchunks = (K + kKC - 1) / kKC;
+    const int nchunks = (K + C::KC - 1) / C::KC;
     for (int ch = 0; ch < nchunks; ++ch) {
         const int buf = ch & 1;
-        if (ch + 1 < nchunks) load_chunk((ch + 1) * kKC, ra, rb);
+        if (ch + 1 < nchunks) load_chunk((ch + 1) * C::KC, ra, rb);
 #pragma unroll
-        for (int kk = 0; kk < kKC; kk += 4) {
-            double av[4], bv[4];
+        for (int kk = 0; kk < C::KC; kk += 4) {
+            T av[4], bv[4];
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][wr + 16 * bi + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
@@ -713,22 +774,21 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<T>::mfma(av[bi], bv[bj], acc[bi][bj]);
         }
         if (ch + 1 < nchunks) {
             store_chunk(buf ^ 1, ra, rb);
             __syncthreads();
         }
     }
-    // epilogue: A22 -= product.  lane l, slot j -> row 4j + l/16, column l%16 of the 16x16 block
+    // epilogue: C -= product
     const bool full = (r0 + kTM <= rend) && (c0 + kTN <= cend);
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int r = r0 + wr + 16 * bi + 4 * j + (lane >> 4);
-            double *row = E + (int64_t)r * ld + c0 + wc + (lane & 15);
+            const int r = r0 + wr + 16 * bi + MF<T>::rowof(lane, j);
+            T *row = E + (int64_t)r * ld + c0 + wc + (lane & 15);
             if (full) {
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj) row[16 * bj] -= acc[bi][bj][j];
@@ -774,78 +834,348 @@ __global__ void k_zero_int(int *p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// ---------------------------------------------------- mixed precision only
+// Back substitution of one 128-row block on the right-hand columns:
+// X_b = U_b^{-1} Y_b, Y_a -= U_ab X_b, X_a = U_a^{-1} Y_a (U_a, U_b: the diagonal
+// 64-blocks, U_ab the block above U_b), in place.  One workgroup per
+// (64-column tile, element).
+template <typename T>
+__global__ void __launch_bounds__(256) k_bsolve(DevMesh dm, SysDesc sd, int e0, int k0, T *__restrict__ Ebase,
+                                                WS<T> ws) {
+    typedef typename MF<T>::acc_t acc_t;
+    const int e = e0 + blockIdx.y;
+    const ElemDims dd = elem_dims(dm, sd, e);
+    if (k0 >= dd.n) return;
+    const int nbo = min(kNBO, dd.n - k0);
+    const int c0 = dd.n + blockIdx.x * 64;
+    if (c0 >= dd.ncols) return;
+    T *E = Ebase + (sd.off[e] - sd.off[e0]);
+    const int64_t ld = dd.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ T sX[kNBO][65];
+    __shared__ T sM[kNB][kNB + 1];
+    for (int t = tid; t < kNBO * 64; t += 256) {
+        const int r = t >> 6, c = t & 63;
+        sX[r][c] = (r < nbo && c0 + c < dd.ncols) ? E[(int64_t)(k0 + r) * ld + c0 + c] : T(0);
+    }
+    const T *ud = ws.d + (int64_t)blockIdx.y * ws.ds;
+    acc_t acc[4];
+    if (nbo > kNB) {
+        for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = ud[3 * kNB * kNB + t];
+        __syncthreads();
+        mfma_64x64<T>(sM, (const T (*)[65])(&sX[kNB][0]), acc, lane, wave);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
+        for (int t = tid; t < kNB * kNB; t += 256) {
+            const int r = t >> 6, c = t & 63;
+            sM[r][c] = (kNB + c < nbo) ? E[(int64_t)(k0 + r) * ld + k0 + kNB + c] : T(0);
+        }
+        __syncthreads();
+        mfma_64x64<T>(sM, (const T (*)[65])(&sX[kNB][0]), acc, lane, wave);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sX[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] -= acc[j][q];
+    }
+    __syncthreads();
+    for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = ud[2 * kNB * kNB + t];
+    __syncthreads();
+    mfma_64x64<T>(sM, sX, acc, lane, wave);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sX[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
+    __syncthreads();
+    for (int t = tid; t < nbo * 64; t += 256) {
+        const int r = t >> 6, c = t & 63;
+        if (c0 + c < dd.ncols) E[(int64_t)(k0 + r) * ld + c0 + c] = sX[r][c];
+    }
+}
+
+__device__ inline void mixed_dims(const DevMesh &dm, int e, int &n, int &f, int64_t &ld, int64_t &ldx) {
+    const int p = dm.elem_p[e];
+    n = 20 * (p + 1) * (p + 1) * (p + 1);
+    f = dm.toff[7 * e + 6];
+    ld = e_ld(n, f);
+    ldx = x_ld(f);
+}
+
+// FP32 copy of the interior rows [A | B R_qu] (padding columns included).
+__global__ void __launch_bounds__(256) k_to32(DevMesh dm, int e0, const double *__restrict__ Ebase,
+                                              float *__restrict__ Mbase) {
+    const int e = e0 + blockIdx.y;
+    int n, f;
+    int64_t ld, ldx;
+    mixed_dims(dm, e, n, f, ld, ldx);
+    const MF<double>::v2 *E = (const MF<double>::v2 *)(Ebase + (dm.E_off[e] - dm.E_off[e0]));
+    MF<float>::v2 *M = (MF<float>::v2 *)(Mbase + (dm.m32_off[e] - dm.m32_off[e0]));
+    const int64_t total = (int64_t)n * ld / 2;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const MF<double>::v2 v = E[i];
+        M[i] = (MF<float>::v2){(float)v.x, (float)v.y};
+    }
+}
+
+// X (FP64, n x x_ld) = the right-hand columns of the FP32 system (MODE 0), or
+// X += them (MODE 1), or X += them and X is also written into E's [B | R_qu]
+// columns (MODE 2, the last refinement step).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_xupdate(DevMesh dm, int e0, const float *__restrict__ Mbase,
+                                                 double *__restrict__ Xbase, double *__restrict__ Ebase) {
+    const int e = e0 + blockIdx.y;
+    int n, f;
+    int64_t ld, ldx;
+    mixed_dims(dm, e, n, f, ld, ldx);
+    const float *M = Mbase + (dm.m32_off[e] - dm.m32_off[e0]);
+    double *X = Xbase + (dm.x_off[e] - dm.x_off[e0]);
+    double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    for (int r = blockIdx.x; r < n; r += gridDim.x)
+        for (int c = threadIdx.x; c < ldx; c += 256) {
+            const double m = (c <= f) ? (double)M[(int64_t)r * ld + n + c] : 0.0;
+            const int64_t i = (int64_t)r * ldx + c;
+            const double x = (MODE == 0) ? m : X[i] + m;
+            X[i] = x;
+            if (MODE == 2 && c <= f) E[(int64_t)r * ld + n + c] = x;
+        }
+}
+
+// Column fields of A that can be nonzero in row field fr (fields: q_(c,j) = 3c+j,
+// u_c = 15+c).  R_q couples q_(c,j) to itself (mass) and to u_c; R_u couples
+// u_c to every u (convective, viscous, mass and tau terms) and to the gradients
+// its fluxes read: the artificial viscosity term only for c = 0, the velocity
+// gradients (q of c' = 0..3) for the momentum rows, all of q for the energy row.
+__device__ inline unsigned a_field_mask(int fr) {
+    if (fr < 15) return (1u << fr) | (1u << (15 + fr / 3));
+    const unsigned u = 0x1Fu << 15;
+    const int c = fr - 15;
+    return c == 0 ? (u | 0x7u) : (c == 4 ? (u | 0x7FFFu) : (u | 0xFFFu));
+}
+
+// FP64 products of the mixed path, 128 x 128 tiles on FP64 matrix cores:
+//   OP 0 (refinement residual): R = [B | R_qu] - A X over rows 0..n-1, stored in
+//        FP32 into the right-hand columns of the FP32 system.  K chunks whose
+//        column fields are structurally zero in every row field of the tile are
+//        skipped (those entries of A are exact zeros).
+//   OP 1 (Schur complement): [S^K | -g^K] = [D | R_uh] - C X over rows n..n+f-1,
+//        written to SK column-major with the last column negated.
+template <int OP>
+__global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, int tiles_m, int tiles_n,
+                                                   const double *__restrict__ Ebase, const double *__restrict__ Xbase,
+                                                   float *__restrict__ Mbase, double *__restrict__ SK) {
+    typedef UpdCfg<double> C;
+    typedef MF<double>::v16 v16;
+    typedef MF<double>::acc_t acc_t;
+    const int total = ne * tiles_m * tiles_n;
+    const int per_xcd = (total + 7) / 8;
+    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= total) return;
+    const int el = w / (tiles_m * tiles_n), t = w % (tiles_m * tiles_n);
+    const int e = e0 + el;
+    int n, f;
+    int64_t ld, ldx;
+    mixed_dims(dm, e, n, f, ld, ldx);
+    const int Mrows = (OP == 0) ? n : f, N = f + 1, K = n;
+    const int r0 = (t / tiles_n) * kTM, c0 = (t % tiles_n) * kTN;
+    if (r0 >= Mrows || c0 >= N) return;
+    const int arow0 = (OP == 0) ? 0 : n;
+    const double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    const double *X = Xbase + (dm.x_off[e] - dm.x_off[e0]);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    __shared__ __attribute__((aligned(16))) double sA[2][kTM][C::SA];
+    __shared__ __attribute__((aligned(16))) double sB[2][C::KC][C::SB];
+    const int ar = tid >> 3, ak = (tid & 7) * C::V;
+    const int bk = tid / C::LPK, bc = (tid % C::LPK) * C::V;
+    const double *arow[4];
+    bool aok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = r0 + 32 * q + ar;
+        aok[q] = row < Mrows;
+        arow[q] = E + (int64_t)(arow0 + min(row, Mrows - 1)) * ld;
+    }
+    const int bcol = c0 + bc;
+    const int bcolc = min(bcol, (N - 1) & ~1);
+    auto load_chunk = [&](int kc, v16 *ra, v16 *rb) {
+        const int gk = kc + ak;
+        const int gkc = min(gk, (K - 1) & ~1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const v16 v = *(const v16 *)(arow[q] + gkc);
+            ra[q].x = (aok[q] && gk < K) ? v.x : 0.0;
+            ra[q].y = (aok[q] && gk + 1 < K) ? v.y : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gk2 = kc + C::KPQ * q + bk;
+            const bool k2ok = gk2 < K;
+            const v16 v = *(const v16 *)(X + (int64_t)min(gk2, K - 1) * ldx + bcolc);
+            rb[q].x = (k2ok && bcol < N) ? v.x : 0.0;
+            rb[q].y = (k2ok && bcol + 1 < N) ? v.y : 0.0;
+        }
+    };
+    auto store_chunk = [&](int buf, const v16 *ra, const v16 *rb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *(v16 *)&sA[buf][32 * q + ar][ak] = ra[q];
+            *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = rb[q];
+        }
+    };
+    // K chunks this tile needs
+    const int Np = n / 20;
+    unsigned rmask = 0xFFFFFu;
+    if (OP == 0) {
+        rmask = 0;
+        const int fr1 = (min(r0 + kTM, Mrows) - 1) / Np;
+        for (int fr = r0 / Np; fr <= fr1; ++fr) rmask |= a_field_mask(fr);
+    }
+    const int nchunks = (K + C::KC - 1) / C::KC;
+    auto needed = [&](int ch) {
+        const int k_lo = ch * C::KC, k_hi = min(k_lo + C::KC, K) - 1;
+        const int f0 = k_lo / Np, f1 = k_hi / Np;
+        const unsigned span = ((2u << f1) - 1u) & ~((1u << f0) - 1u);
+        return (rmask & span) != 0u;
+    };
+    auto next_needed = [&](int ch) {
+        while (ch < nchunks && !needed(ch)) ++ch;
+        return ch;
+    };
+    acc_t acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = (acc_t){0.0, 0.0, 0.0, 0.0};
+    v16 ra[4], rb[4];
+    int ch = next_needed(0);
+    int buf = 0;
+    if (ch < nchunks) {
+        load_chunk(ch * C::KC, ra, rb);
+        store_chunk(0, ra, rb);
+        __syncthreads();
+    }
+    while (ch < nchunks) {
+        const int nx = next_needed(ch + 1);
+        if (nx < nchunks) load_chunk(nx * C::KC, ra, rb);
+#pragma unroll
+        for (int kk = 0; kk < C::KC; kk += 4) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][wr + 16 * bi + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][kk + (lane >> 4)][wc + 16 * bj + (lane & 15)];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<double>::mfma(av[bi], bv[bj], acc[bi][bj]);
+        }
+        if (nx < nchunks) {
+            store_chunk(buf ^ 1, ra, rb);
+            __syncthreads();
+        }
+        buf ^= 1;
+        ch = nx;
+    }
+    // epilogue: out = Cin - product
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + wr + 16 * bi + MF<double>::rowof(lane, j);
+            if (r >= Mrows) continue;
+            const double *cin = E + (int64_t)(arow0 + r) * ld + n;
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const int c = c0 + wc + 16 * bj + (lane & 15);
+                if (c >= N) continue;
+                const double v = cin[c] - acc[bi][bj][j];
+                if (OP == 0) {
+                    float *M = Mbase + (dm.m32_off[e] - dm.m32_off[e0]);
+                    M[(int64_t)r * ld + n + c] = (float)v;
+                } else {
+                    SK[dm.SK_off[e] + (int64_t)c * f + r] = (c == f) ? -v : v;
+                }
+            }
+        }
+}
+
 }  // namespace
 
-// Run the bordered elimination on systems e0..e0+ne-1 described by sd.
-template <int TAG>
-static int run_bordered_lu_t(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, double *E, int *info,
-                             void *workv, int maxn, int maxm, int maxf_rows, hipStream_t s) {
+// Blocked LU of the systems e0..e0+ne-1 described by sd (bordered: trace rows
+// included when maxf_rows > 0).  ws: per-element workspace; with `persist` every
+// 128-column block keeps its own slot (ws strides hold all blocks).
+template <typename T, int TAG>
+static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, int *info, WS<T> ws, bool persist,
+                  int maxn, int maxm, int maxc, int maxf_rows, hipStream_t s) {
     const DevMesh &dm = ctx->dm;
-    double *wsd = (double *)workv;
-    int *wsi = (int *)((char *)workv + sizeof(double) * (size_t)ne * kWsDbl);
     hipLaunchKernelGGL(k_zero_int, dim3((ne + 255) / 256), dim3(256), 0, s, info + e0, ne);
     const int R = (maxn + kPT - 1) / kPT;
-    auto crows = [&](int kp, int slot) {
-        if (maxf_rows > 0)
-            hipLaunchKernelGGL((k_crows<TAG>), dim3((maxf_rows + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, kp, slot, E,
-                               (const double *)wsd);
-    };
-    auto panel = [&](int k0, int slot, int kbase) {
-        if (R <= 1) hipLaunchKernelGGL((k_panel<1, TAG>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, k0, slot, kbase, E, wsd, wsi, info);
-        else if (R <= 2) hipLaunchKernelGGL((k_panel<2, TAG>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, k0, slot, kbase, E, wsd, wsi, info);
-        else if (R <= 3) hipLaunchKernelGGL((k_panel<3, TAG>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, k0, slot, kbase, E, wsd, wsi, info);
-        else hipLaunchKernelGGL((k_panel<5, TAG>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, k0, slot, kbase, E, wsd, wsi, info);
-        crows(k0, slot);
-    };
-    auto update = [&](int k0, int KW, int CW, int rows, int cols) {
-        if (rows <= 0 || cols <= 0) return;
-        const int tm = (rows + kTM - 1) / kTM, tn = (cols + kTN - 1) / kTN;
-        const int total = ne * tm * tn;
-        hipLaunchKernelGGL((k_update<TAG>), dim3((total + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, k0, KW, CW, tm,
-                           tn, E);
-    };
     if (R > 5) return (int)hipErrorInvalidValue;
     for (int k0 = 0; k0 < maxn; k0 += kNBO) {
-        panel(k0, 0, k0);
+        WS<T> wb = ws;
+        if (persist) {
+            wb.d += (int64_t)(k0 / kNBO) * kWsDbl;
+            wb.i += (int64_t)(k0 / kNBO) * kWsInt;
+        }
+        auto panel = [&](int kp, int slot) {
+            if (R <= 1) hipLaunchKernelGGL((k_panel<1, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
+            else if (R <= 2) hipLaunchKernelGGL((k_panel<2, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
+            else if (R <= 3) hipLaunchKernelGGL((k_panel<3, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
+            else hipLaunchKernelGGL((k_panel<5, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
+            if (maxf_rows > 0)
+                hipLaunchKernelGGL((k_crows<TAG, T>), dim3((maxf_rows + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, kp,
+                                   slot, E, wb);
+        };
+        auto update = [&](int KW, int CW, int rows, int cols) {
+            if (rows <= 0 || cols <= 0) return;
+            const int tm = (rows + kTM - 1) / kTM, tn = (cols + kTN - 1) / kTN;
+            const int total = ne * tm * tn;
+            hipLaunchKernelGGL((k_update<T, TAG, kRangeLU>), dim3((total + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne,
+                               k0, KW, CW, tm, tn, E);
+        };
+        const int ncol = maxc - k0;
+        panel(k0, 0);
         if (maxn - k0 > kNB) {
             // rest of the 128-column block, then its second panel
-            hipLaunchKernelGGL((k_rowperm<0, TAG>), dim3(1, ne), dim3(256), 0, s, dm, sd, e0, k0, kNBO, E,
-                               (const double *)wsd, (const int *)wsi);
-            update(k0, kNB, kNBO, maxm - k0, kNB);
-            panel(k0 + kNB, 1, k0);
-            hipLaunchKernelGGL((k_rowperm<1, TAG>), dim3(1, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, E,
-                               (const double *)wsd, (const int *)wsi);
+            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3(1, ne), dim3(256), 0, s, dm, sd, e0, k0, kNBO, 0, E, wb);
+            update(kNB, kNBO, maxm - k0, kNB);
+            panel(k0 + kNB, 1);
+            hipLaunchKernelGGL((k_rowperm<1, TAG, T>), dim3(1, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0, E, wb);
             // trailing columns: 128-row permutation + block solve, K = 128 update
-            const int ncol = maxm + 1 - k0;
-            hipLaunchKernelGGL((k_rowperm<2, TAG>), dim3((ncol + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, 0,
-                               E, (const double *)wsd, (const int *)wsi);
-            update(k0, kNBO, 0, maxm - k0, ncol);
+            hipLaunchKernelGGL((k_rowperm<2, TAG, T>), dim3((ncol + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
+                               E, wb);
+            update(kNBO, 0, maxm - k0, ncol);
         } else {
-            const int ncol = maxm + 1 - k0;
-            hipLaunchKernelGGL((k_rowperm<0, TAG>), dim3((ncol + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, 0,
-                               E, (const double *)wsd, (const int *)wsi);
-            update(k0, kNB, 0, maxm - k0, ncol);
+            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3((ncol + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
+                               E, wb);
+            update(kNB, 0, maxm - k0, ncol);
         }
     }
     return (int)hipGetLastError();
 }
 
-static int run_bordered_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, double *E, int *info,
-                           void *workv, int maxn, int maxm, int maxf_rows, hipStream_t s) {
-    if (sd.mode == 0) return run_bordered_lu_t<0>(ctx, sd, e0, ne, E, info, workv, maxn, maxm, maxf_rows, s);
-    return run_bordered_lu_t<1>(ctx, sd, e0, ne, E, info, workv, maxn, maxm, maxf_rows, s);
+static void chunk_max(const hdg_ctx *ctx, int e0, int ne, int *maxn, int *maxf) {
+    *maxn = 0;
+    *maxf = 0;
+    for (int e = e0; e < e0 + ne; ++e) {
+        *maxn = std::max(*maxn, ctx->elem_n[e]);
+        *maxf = std::max(*maxf, ctx->elem_f[e]);
+    }
 }
 
 int launch_condense_fp64(const hdg_ctx *ctx, int e0, int ne, double *E, double *SK, int *info, void *work,
                          hipStream_t s) {
-    int maxn = 0, maxm = 0, maxf = 0;
-    for (int e = e0; e < e0 + ne; ++e) {
-        maxn = std::max(maxn, ctx->elem_n[e]);
-        maxm = std::max(maxm, ctx->elem_n[e] + ctx->elem_f[e]);
-        maxf = std::max(maxf, ctx->elem_f[e]);
-    }
+    int maxn, maxf, maxm = 0;
+    chunk_max(ctx, e0, ne, &maxn, &maxf);
+    for (int e = e0; e < e0 + ne; ++e) maxm = std::max(maxm, ctx->elem_n[e] + ctx->elem_f[e]);
     const SysDesc sd{0, ctx->dm.E_off};
-    int err = run_bordered_lu(ctx, sd, e0, ne, E, info, work, maxn, maxm, maxf, s);
+    WS<double> ws{(double *)work, (int *)((char *)work + sizeof(double) * (size_t)ne * kWsDbl), kWsDbl, kWsInt};
+    int err = run_lu<double, 0>(ctx, sd, e0, ne, E, info, ws, false, maxn, maxm, maxm + 1, maxf, s);
     if (err) return err;
     hipLaunchKernelGGL(k_extract, dim3((maxf + 1 + 31) / 32, (maxf + 31) / 32, ne), dim3(256), 0, s, ctx->dm, sd,
                        e0, (const double *)E, SK);
@@ -862,7 +1192,102 @@ size_t bordered_lu_work(const hdg_ctx *ctx, int ne) {
 int run_asm_inversion(const hdg_ctx *ctx, double *sys, int *info, void *iwork, hipStream_t s) {
     const SysDesc sd{1, ctx->dm.asmsys_off};
     const int maxf = ctx->max_f + (ctx->max_f & 1);
-    return run_bordered_lu(ctx, sd, 0, ctx->n_elem, sys, info, iwork, maxf, 2 * maxf, maxf, s);
+    const int ne = ctx->n_elem;
+    WS<double> ws{(double *)iwork, (int *)((char *)iwork + sizeof(double) * (size_t)ne * kWsDbl), kWsDbl, kWsInt};
+    return run_lu<double, 1>(ctx, sd, 0, ne, sys, info, ws, false, maxf, 2 * maxf, 2 * maxf + 1, maxf, s);
+}
+
+// ---------------------------------------------------------------- mixed path
+// Workspace of a chunk: FP32 systems | X (FP64) | per-block LU records (FP32 values, ints).
+struct MixedLayout {
+    size_t m_off, x_off, wd_off, wi_off, total;
+    int nblk;
+};
+static size_t r256(size_t b) { return (b + 255) / 256 * 256; }
+static MixedLayout mixed_layout(const hdg_ctx *ctx, int e0, int ne) {
+    int maxn, maxf;
+    chunk_max(ctx, e0, ne, &maxn, &maxf);
+    MixedLayout L;
+    L.nblk = std::max(1, (maxn + kNBO - 1) / kNBO);
+    L.m_off = 0;
+    L.x_off = L.m_off + r256(sizeof(float) * (size_t)(ctx->m32_off[e0 + ne] - ctx->m32_off[e0]));
+    L.wd_off = L.x_off + r256(sizeof(double) * (size_t)(ctx->x_off[e0 + ne] - ctx->x_off[e0]));
+    L.wi_off = L.wd_off + r256(sizeof(float) * (size_t)ne * L.nblk * kWsDbl);
+    L.total = L.wi_off + r256(sizeof(int) * (size_t)ne * L.nblk * kWsInt);
+    return L;
+}
+
+size_t condense_mixed_work_bytes(const hdg_ctx *ctx, int e0, int ne) { return mixed_layout(ctx, e0, ne).total; }
+
+int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double *E, double *SK, int *info,
+                          void *work, hipStream_t s) {
+    const DevMesh &dm = ctx->dm;
+    int maxn, maxf;
+    chunk_max(ctx, e0, ne, &maxn, &maxf);
+    const MixedLayout L = mixed_layout(ctx, e0, ne);
+    char *wb = (char *)work;
+    float *M = (float *)(wb + L.m_off);
+    double *X = (double *)(wb + L.x_off);
+    WS<float> ws{(float *)(wb + L.wd_off), (int *)(wb + L.wi_off), (int64_t)L.nblk * kWsDbl,
+                 (int64_t)L.nblk * kWsInt};
+    const SysDesc sd{2, dm.m32_off};
+    const int rhs_cols = maxf + 1;
+    const dim3 rhs_grid((rhs_cols + 63) / 64, ne);
+    auto block_ws = [&](int k0) {
+        WS<float> w = ws;
+        w.d += (int64_t)(k0 / kNBO) * kWsDbl;
+        w.i += (int64_t)(k0 / kNBO) * kWsInt;
+        return w;
+    };
+    const int tn = (rhs_cols + kTN - 1) / kTN;
+    auto rhs_update = [&](bool fwd, int k0, int rows) {
+        if (rows <= 0) return;
+        const int tm = (rows + kTM - 1) / kTM;
+        const dim3 grid((ne * tm * tn + 7) / 8 * 8);
+        if (fwd)
+            hipLaunchKernelGGL((k_update<float, 2, kRangeFwd>), grid, dim3(256), 0, s, dm, sd, e0, ne, k0, kNBO, 0, tm,
+                               tn, M);
+        else
+            hipLaunchKernelGGL((k_update<float, 2, kRangeBwd>), grid, dim3(256), 0, s, dm, sd, e0, ne, k0, kNBO, 0, tm,
+                               tn, M);
+    };
+    auto back_solve = [&]() {
+        for (int k0 = (maxn - 1) / kNBO * kNBO; k0 >= 0; k0 -= kNBO) {
+            hipLaunchKernelGGL((k_bsolve<float>), rhs_grid, dim3(256), 0, s, dm, sd, e0, k0, M, block_ws(k0));
+            rhs_update(false, k0, k0);
+        }
+    };
+    auto forward_solve = [&]() {
+        for (int k0 = 0; k0 < maxn; k0 += kNBO) {
+            hipLaunchKernelGGL((k_rowperm<2, 2, float>), rhs_grid, dim3(256), 0, s, dm, sd, e0, k0, 0, 1, M,
+                               block_ws(k0));
+            rhs_update(true, k0, maxn - k0 - kNBO);
+        }
+    };
+    const dim3 elem_grid(64, ne);
+    hipLaunchKernelGGL(k_to32, elem_grid, dim3(256), 0, s, dm, e0, (const double *)E, M);
+    // FP32 LU of A with the forward substitution of [B | R_qu] carried along, then X_0
+    int err = run_lu<float, 2>(ctx, sd, e0, ne, M, info, ws, true, maxn, maxn, maxn + maxf + 1, 0, s);
+    if (err) return err;
+    back_solve();
+    hipLaunchKernelGGL(k_xupdate<0>, elem_grid, dim3(256), 0, s, dm, e0, (const float *)M, X, E);
+    const int tm_r = (maxn + kTM - 1) / kTM;
+    for (int it = 0; it < refine; ++it) {
+        // R = [B | R_qu] - A X in FP64 (into the FP32 right-hand columns), d = A^{-1} R, X += d
+        hipLaunchKernelGGL(k_gemm64<0>, dim3((ne * tm_r * tn + 7) / 8 * 8), dim3(256), 0, s, dm, e0, ne, tm_r, tn,
+                           (const double *)E, (const double *)X, M, SK);
+        forward_solve();
+        back_solve();
+        if (it + 1 < refine)
+            hipLaunchKernelGGL(k_xupdate<1>, elem_grid, dim3(256), 0, s, dm, e0, (const float *)M, X, E);
+        else
+            hipLaunchKernelGGL(k_xupdate<2>, elem_grid, dim3(256), 0, s, dm, e0, (const float *)M, X, E);
+    }
+    // [S^K | -g^K] = [D | R_uh] - C X (FP64), stored as [S^K | g^K]
+    const int tm_s = (maxf + kTM - 1) / kTM;
+    hipLaunchKernelGGL(k_gemm64<1>, dim3((ne * tm_s * tn + 7) / 8 * 8), dim3(256), 0, s, dm, e0, ne, tm_s, tn,
+                       (const double *)E, (const double *)X, M, SK);
+    return (int)hipGetLastError();
 }
 
 }  // namespace hdg

@@ -6,6 +6,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.linalg as sla
 
 from gpu_common import (O, RTOL_FP64, assert_rel, bsr_blocks, e_view, oracle_condensed, recovery_checks, rel_err,
                         residual_scale, sk_view)
@@ -94,6 +95,50 @@ def test_mixed_degrees_dirichlet_walls_ragged_chunks():
     wl = _wl_walls()
     assert wl.mesh.face_bc.sum() > 0 and len(set(wl.mesh.elem_p.tolist())) > 1
     _run_and_compare(wl, chunk=5)
+
+
+def _mixed_condense_and_compare(wl, chunk=None):
+    """Mixed condensation against the oracle: S^K and g^K to 1e-10 relative per
+    element; the stored X = A^{-1}[B | R_qu] within 10x of the same recipe run
+    through LAPACK (FP32 LU, one FP64-residual refinement step)."""
+    import torch
+    from paper_2608_27863_amd import hdg, pipeline
+    st = pipeline.NewtonStep(wl, prec=hdg.HDG_MIXED, chunk=chunk)
+    st.residual_jacobian()
+    st.condense()
+    torch.cuda.synchronize()
+    assert np.all(st.info.cpu().numpy() == 0)
+    ora = oracle_condensed(wl)
+    ctx = st.ctx
+    SK, E = st.SK.cpu().numpy(), st.E.cpu().numpy()
+    worst = [0.0, 0.0, 0.0]
+    ref = 0.0
+    for e in range(wl.mesh.n_elem):
+        S, g = sk_view(ctx, SK, e)
+        n, f = int(ctx.layout["elem_n"][e]), int(ctx.layout["elem_f"][e])
+        o = ctx.layout["E_off"]
+        a = E[int(o[e]):int(o[e + 1])]
+        X = a.reshape(n + f, a.size // (n + f))[:n, n:n + f + 1]
+        errs = (rel_err(S, ora[e]["SK"]), rel_err(g, ora[e]["gK"]), rel_err(X, ora[e]["X"]))
+        worst = [max(w, x) for w, x in zip(worst, errs)]
+        Eo = ora[e]["E"]
+        lu = sla.lu_factor(Eo[:n, :n].astype(np.float32))
+        solve = lambda R: sla.lu_solve(lu, R.astype(np.float32)).astype(np.float64)
+        X0 = solve(Eo[:n, n:])
+        ref = max(ref, rel_err(X0 + solve(Eo[:n, n:] - Eo[:n, :n] @ X0), ora[e]["X"]))
+    print(f"  mixed: S^K {worst[0]:.2e}  g^K {worst[1]:.2e}  X {worst[2]:.2e} (LAPACK recipe {ref:.2e})", flush=True)
+    assert worst[0] <= 1e-10 and worst[1] <= 1e-10 and worst[2] <= max(10.0 * ref, 1e-13)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_mixed_precision_degrees(p):
+    print(f"[shapes] mixed precision, p={p}, 2x2x2 perturbed periodic", flush=True)
+    _mixed_condense_and_compare(_wl_periodic((2, 2, 2), p))
+
+
+def test_mixed_precision_mixed_degrees_ragged_chunks():
+    print("[shapes] mixed precision, mixed p, Dirichlet walls, chunks of 5", flush=True)
+    _mixed_condense_and_compare(_wl_walls(), chunk=5)
 
 
 def test_element_meeting_a_face_twice():

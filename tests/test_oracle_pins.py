@@ -296,6 +296,37 @@ def test_condensation_matches_lapack():
         assert np.linalg.norm(A @ dW + B @ dUh + Rq) < 1e-11 * np.linalg.norm(Rq)
 
 
+@pytest.mark.parametrize("nu_amp", [0.0, 5e-4])
+def test_interior_jacobian_field_coupling(nu_amp):
+    """Zero blocks of A that follow from eqs. hdg-grad and hdg-cons (fields
+    q_(c,j) = 3c+j, u_c = 15+c; one N_p x N_p block per field pair):
+    R_q of q_(c,j) involves only q_(c,j) (mass) and u_c; the mass row of R_u
+    reads gradients only through the artificial-viscosity flux (nu q_0); the
+    momentum rows read the velocity gradients (q of c' <= 3), never q_4.
+    The mixed-precision residual relies on these blocks being exactly zero."""
+    wl = _wl(n=2, p=2, perturb=0.1, nu_amp=nu_amp, mach=1.25)
+    sz = O.Sizes(wl.mesh)
+    E = O.element_system(wl, 3, sz)
+    n = sz.n(3)
+    Np = n // 20
+    A = O.split(E, n)[0]
+    blk = lambda r, c: A[r * Np:(r + 1) * Np, c * Np:(c + 1) * Np]
+    for c in range(5):
+        for j in range(3):
+            r = 3 * c + j
+            for col in range(20):
+                nonzero = np.any(blk(r, col) != 0.0)
+                assert nonzero == (col in (r, 15 + c)), (r, col)
+    for col in range(3, 15):
+        assert not np.any(blk(15, col) != 0.0), col           # mass equation: only q_0 via nu
+    assert np.any(blk(15, 0) != 0.0) == (nu_amp > 0)
+    for c in (1, 2, 3):
+        for col in range(12, 15):
+            assert not np.any(blk(15 + c, col) != 0.0), (c, col)   # momentum: no energy gradient
+        assert np.any(blk(15 + c, 3 * c) != 0.0)                  # its own velocity gradient
+    assert np.any(blk(19, 12) != 0.0)                             # energy: heat flux
+
+
 def _condensed(wl):
     sz = O.Sizes(wl.mesh)
     Es = [O.element_system(wl, e, sz) for e in range(wl.mesh.n_elem)]
