@@ -50,7 +50,7 @@ struct DevMesh {
     const int64_t *SK_off;     // [n_elem+1]
     const int64_t *asm_off;    // [n_elem+1]
     const int64_t *qp_off;     // [n_elem+1]
-    const int64_t *asmsys_off; // [n_elem+1] Schwarz inversion systems (2f x ld doubles)
+    const int64_t *asmsys_off; // [n_elem+1] Schwarz inversion systems (2m x ld entries, m = asm_pad(f))
     const int64_t *tloc_off;   // [n_elem+1] prefix sums of f_e (element-local trace vectors)
     const int64_t *m32_off;    // [n_elem+1] FP32 interior systems [A | B R_qu] (n x e_ld floats)
     const int64_t *x_off;      // [n_elem+1] X = A^{-1}[B | R_qu] (n x x_ld doubles)
@@ -77,6 +77,10 @@ struct Phys {
 
 // Element-system row stride (doubles): n + f + 1 rounded up to a multiple of 8.
 __host__ __device__ inline int64_t e_ld(int n, int f) { return ((int64_t)(n + f + 1) + 7) / 8 * 8; }
+// Size of an element's Schwarz inversion system: f rounded up to a multiple of 4
+// (extra unknowns are decoupled), so that every panel width and column offset
+// allows 16-byte FP32 and FP64 accesses.
+__host__ __device__ inline int asm_pad(int f) { return (f + 3) & ~3; }
 // Row stride of X (doubles): f + 1 rounded up to a multiple of 8.
 __host__ __device__ inline int64_t x_ld(int f) { return ((int64_t)(f + 1) + 7) / 8 * 8; }
 
@@ -109,7 +113,7 @@ int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double
                           int *info, void *work, hipStream_t s);
 size_t condense_mixed_work_bytes(const hdg_ctx *ctx, int e0, int ne);
 size_t bordered_lu_work(const hdg_ctx *ctx, int ne);
-int run_asm_inversion(const hdg_ctx *ctx, double *sys, int *info, void *work, hipStream_t s);
+int run_asm_inversion(const hdg_ctx *ctx, int prec, void *sys, int *info, void *work, hipStream_t s);
 int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, hipStream_t s);
 int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *y, hipStream_t s);
 int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info,

@@ -70,6 +70,7 @@ constexpr int kNB = 64;       // panel width
 constexpr int kNBO = 128;     // pivot columns per trailing update
 constexpr int kW = 8;         // register sub-panel width
 constexpr int kPT = 512;      // panel kernel threads
+constexpr int kRPC = 32;      // columns per k_rowperm workgroup
 static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptions");
 // A recorded permutation of w swaps (row base+jj <-> piv[jj]): [0] = number of
 // displaced rows, [1 .. W] source row of each top row, then (dst, src) pairs.
@@ -96,7 +97,7 @@ struct ElemDims {
 };
 // Systems factored here: mode 0 = element systems (n = 20 N_p, f = f_e, all
 // n + f rows); mode 1 = Schwarz inversion systems [[S_r, I], [I, 0]] (n = f = f_r
-// rounded up to even); mode 2 = FP32 interior rows [A | B R_qu] (n rows).
+// rounded up to a multiple of 4); mode 2 = FP32 interior rows [A | B R_qu] (n rows).
 struct SysDesc {
     int mode;
     const int64_t *off;  // [n_elem+1] offsets (elements) of the systems
@@ -108,10 +109,8 @@ __device__ inline ElemDims elem_dims(const DevMesh &dm, const SysDesc &sd, int e
         d.n = 20 * (p + 1) * (p + 1) * (p + 1);
         d.f = dm.toff[7 * e + 6];
     } else {
-        // Schwarz system of an element with an odd f carries one extra decoupled
-        // unknown, so that every panel width and column offset stays even
-        const int f = dm.toff[7 * e + 6];
-        d.n = f + (f & 1);
+        // Schwarz system padded with decoupled unknowns to a multiple of 4
+        d.n = asm_pad(dm.toff[7 * e + 6]);
         d.f = d.n;
     }
     d.mrows = (sd.mode == 2) ? d.n : d.n + d.f;
@@ -485,7 +484,23 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     if (tid == 0 && info_k && info[e] == 0) info[e] = info_k;
 }
 
-// acc (rows 16 wave .. +15, 64 columns) = Ls (64x64) * X (64 x 64), both in LDS.
+// acc (rows 16 wave .. +15, C columns) = Ls (64x64) * X (64 x C), both in LDS.
+template <typename T, int C>
+__device__ inline void mfma_64xc(const T (*Ls)[kNB + 1], const T (*X)[C + 1], typename MF<T>::acc_t acc[C / 16],
+                                 int lane, int wave) {
+#pragma unroll
+    for (int j = 0; j < C / 16; ++j) acc[j] = (typename MF<T>::acc_t){T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+    for (int kk = 0; kk < kNB; kk += 4) {
+        const T a = Ls[16 * wave + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < C / 16; ++j) {
+            const T b = X[kk + (lane >> 4)][16 * j + (lane & 15)];
+            acc[j] = MF<T>::mfma(a, b, acc[j]);
+        }
+    }
+}
+
 template <typename T>
 __device__ inline void mfma_64x64(const T (*Ls)[kNB + 1], const T (*X)[65], typename MF<T>::acc_t acc[4], int lane,
                                   int wave) {
@@ -545,7 +560,7 @@ __global__ void __launch_bounds__(256) k_crows(DevMesh dm, SysDesc sd, int e0, i
 //         U_a = La^{-1} X_a, X_b -= L_ba U_a, U_b = Lb^{-1} X_b, on the trailing
 //         columns (rhs = 1: on the right-hand columns n.. only, which replays the
 //         block's forward substitution on a new right-hand side)
-// One workgroup per (64-column tile, element).
+// One workgroup per (32-column tile, element).
 template <int MODE, int TAG, typename T>
 __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0, int k0, int CW, int rhs,
                                                  T *__restrict__ Ebase, WS<T> ws) {
@@ -571,12 +586,12 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
         c_end = dd.ncols;
         base = k0; nrows = nbo; permoff = (nbo > kNB) ? kWsPerm128 : kWsPerm0;
     }
-    const int c0 = c_begin + blockIdx.x * 64;
+    const int c0 = c_begin + blockIdx.x * kRPC;
     if (c0 >= c_end) return;  // uniform per block
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ T sX[kNBO][65];
+    __shared__ T sX[kNBO][kRPC + 1];
     __shared__ T sM[kNB][kNB + 1];
     __shared__ int sperm[kPerm128];
     const int *wi = ws.i + (int64_t)blockIdx.y * ws.is;
@@ -585,19 +600,19 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
     for (int t = tid; t < permlen; t += 256) sperm[t] = wi[permoff + t];
     __syncthreads();
     // gather the permuted top rows, then move the displaced rows
-    for (int t = tid; t < nrows * 64; t += 256) {
-        const int r = t >> 6, c = t & 63;
+    for (int t = tid; t < nrows * kRPC; t += 256) {
+        const int r = t / kRPC, c = t % kRPC;
         sX[r][c] = (c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : T(0);
     }
-    for (int t = tid; t < (kNBO - nrows) * 64; t += 256) sX[nrows + (t >> 6)][t & 63] = T(0);
+    for (int t = tid; t < (kNBO - nrows) * kRPC; t += 256) sX[nrows + t / kRPC][t % kRPC] = T(0);
     // a top row's source may be a displaced row: its old content must be read
     // before the displaced copies overwrite it
     __syncthreads();
     // displaced rows take original top rows, which are rewritten only after the
     // next barrier
     const int nd = sperm[0];
-    for (int t = tid; t < nd * 64; t += 256) {
-        const int d = t >> 6, c = t & 63;
+    for (int t = tid; t < nd * kRPC; t += 256) {
+        const int d = t / kRPC, c = t % kRPC;
         if (c0 + c < c_end) {
             const int dst = sperm[1 + W + 2 * d], src = sperm[1 + W + 2 * d + 1];
             E[(int64_t)dst * ld + c0 + c] = E[(int64_t)src * ld + c0 + c];
@@ -606,14 +621,14 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
     if (MODE == 1) __syncthreads();
     if (MODE != 1) {
         const T *la = ws.d + (int64_t)blockIdx.y * ws.ds;
-        acc_t acc[4];
+        acc_t acc[kRPC / 16];
         // U_a = La^{-1} X_a
         for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = la[t];
         __syncthreads();
-        mfma_64x64<T>(sM, sX, acc, lane, wave);
+        mfma_64xc<T, kRPC>(sM, sX, acc, lane, wave);
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kRPC / 16; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) sX[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
         if (nrows > kNB) {
@@ -624,10 +639,10 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
                 sM[r][c] = (kNB + r < nrows) ? E[(int64_t)(base + kNB + r) * ld + base + c] : T(0);
             }
             __syncthreads();
-            mfma_64x64<T>(sM, sX, acc, lane, wave);
+            mfma_64xc<T, kRPC>(sM, sX, acc, lane, wave);
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < kRPC / 16; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] -= acc[j][q];
@@ -635,18 +650,18 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
             __syncthreads();
             for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = la[kNB * kNB + t];
             __syncthreads();
-            mfma_64x64<T>(sM, (const T (*)[65])(&sX[kNB][0]), acc, lane, wave);
+            mfma_64xc<T, kRPC>(sM, (const T (*)[kRPC + 1])(&sX[kNB][0]), acc, lane, wave);
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < kRPC / 16; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
         }
         __syncthreads();
     }
-    for (int t = tid; t < nrows * 64; t += 256) {
-        const int r = t >> 6, c = t & 63;
+    for (int t = tid; t < nrows * kRPC; t += 256) {
+        const int r = t / kRPC, c = t % kRPC;
         if (c0 + c < c_end) E[(int64_t)(base + r) * ld + c0 + c] = sX[r][c];
     }
 }
@@ -660,8 +675,7 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
 //              right-hand columns)
 //   kRangeBwd: rows [0, k0), columns [n, ncols)    (back substitution: U12 X2)
 // 128 x 128 tile per workgroup, K in chunks of 16 (FP64) or 32 (FP32) values
-// double-buffered through LDS, matrix cores into zero-initialised accumulators,
-// the subtraction in the epilogue.
+// double-buffered through LDS, matrix cores; C is read before the K loop.
 constexpr int kRangeLU = 0, kRangeFwd = 1, kRangeBwd = 2;
 constexpr int kTM = 128, kTN = 128;
 template <typename T> struct UpdCfg {
@@ -747,15 +761,37 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     auto store_chunk = [&](int buf, const v16 *ra, const v16 *rb) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            *(v16 *)&sA[buf][32 * q + ar][ak] = ra[q];
+            *(v16 *)&sA[buf][32 * q + ar][ak] = (sizeof(T) == 8) ? -ra[q] : ra[q];
             *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = rb[q];
         }
     };
+    // C is read at the start so that its loads overlap the operand loads.  FP64:
+    // the accumulators start from C and A enters LDS negated (the epilogue only
+    // stores).  FP32: C waits in registers of its own and the product is
+    // accumulated from zero, so that every FP32 rounding stays at the scale of
+    // the product rather than of C.
+    constexpr bool kOntoC = sizeof(T) == 8;
     acc_t acc[4][4];
+    acc_t cpre[kOntoC ? 1 : 4][4];
+    const bool full = (r0 + kTM <= rend) && (c0 + kTN <= cend);
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = (acc_t){T(0), T(0), T(0), T(0)};
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + wr + 16 * bi + MF<T>::rowof(lane, j);
+            const T *row = E + (int64_t)min(r, rend - 1) * ld + c0 + wc + (lane & 15);
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const bool ok = full || (r < rend && c0 + wc + 16 * bj + (lane & 15) < cend);
+                const T c = ok ? row[16 * bj] : T(0);
+                if constexpr (kOntoC) {
+                    acc[bi][bj][j] = c;
+                } else {
+                    cpre[bi][bj][j] = c;
+                    acc[bi][bj][j] = T(0);
+                }
+            }
+        }
     v16 ra[4], rb[4];
     load_chunk(0, ra, rb);
     store_chunk(0, ra, rb);
@@ -781,21 +817,23 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
             __syncthreads();
         }
     }
-    // epilogue: C -= product
-    const bool full = (r0 + kTM <= rend) && (c0 + kTN <= cend);
+    // epilogue: C = C - A B
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = r0 + wr + 16 * bi + MF<T>::rowof(lane, j);
             T *row = E + (int64_t)r * ld + c0 + wc + (lane & 15);
+            T v[4];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) v[bj] = kOntoC ? acc[bi][bj][j] : cpre[kOntoC ? 0 : bi][bj][j] - acc[bi][bj][j];
             if (full) {
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) row[16 * bj] -= acc[bi][bj][j];
+                for (int bj = 0; bj < 4; ++bj) row[16 * bj] = v[bj];
             } else if (r < rend) {
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj)
-                    if (c0 + wc + 16 * bj + (lane & 15) < cend) row[16 * bj] -= acc[bi][bj][j];
+                    if (c0 + wc + 16 * bj + (lane & 15) < cend) row[16 * bj] = v[bj];
             }
         }
 }
@@ -1142,16 +1180,16 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
         panel(k0, 0);
         if (maxn - k0 > kNB) {
             // rest of the 128-column block, then its second panel
-            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3(1, ne), dim3(256), 0, s, dm, sd, e0, k0, kNBO, 0, E, wb);
+            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, kNBO, 0, E, wb);
             update(kNB, kNBO, maxm - k0, kNB);
             panel(k0 + kNB, 1);
-            hipLaunchKernelGGL((k_rowperm<1, TAG, T>), dim3(1, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0, E, wb);
+            hipLaunchKernelGGL((k_rowperm<1, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0, E, wb);
             // trailing columns: 128-row permutation + block solve, K = 128 update
-            hipLaunchKernelGGL((k_rowperm<2, TAG, T>), dim3((ncol + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
+            hipLaunchKernelGGL((k_rowperm<2, TAG, T>), dim3((ncol + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
                                E, wb);
             update(kNBO, 0, maxm - k0, ncol);
         } else {
-            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3((ncol + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
+            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3((ncol + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
                                E, wb);
             update(kNB, 0, maxm - k0, ncol);
         }
@@ -1187,14 +1225,19 @@ size_t bordered_lu_work(const hdg_ctx *ctx, int ne) {
     return sizeof(double) * (size_t)ne * kWsDbl + sizeof(int) * (size_t)ne * kWsInt;
 }
 
-// Schwarz blocks: systems [[S_r, I], [I, 0]] in `sys` (offsets asmsys_off), eliminated
-// over the first f_r columns; the trailing block is -S_r^{-1}.
-int run_asm_inversion(const hdg_ctx *ctx, double *sys, int *info, void *iwork, hipStream_t s) {
+// Schwarz blocks: systems [[S_r, I], [I, 0]] in `sys` (offsets asmsys_off, FP64 or
+// FP32 entries), eliminated over the first m_r columns; the trailing block is -S_r^{-1}.
+int run_asm_inversion(const hdg_ctx *ctx, int prec, void *sys, int *info, void *iwork, hipStream_t s) {
     const SysDesc sd{1, ctx->dm.asmsys_off};
-    const int maxf = ctx->max_f + (ctx->max_f & 1);
+    const int maxf = asm_pad(ctx->max_f);
     const int ne = ctx->n_elem;
-    WS<double> ws{(double *)iwork, (int *)((char *)iwork + sizeof(double) * (size_t)ne * kWsDbl), kWsDbl, kWsInt};
-    return run_lu<double, 1>(ctx, sd, 0, ne, sys, info, ws, false, maxf, 2 * maxf, 2 * maxf + 1, maxf, s);
+    int *wi = (int *)((char *)iwork + sizeof(double) * (size_t)ne * kWsDbl);
+    if (prec == HDG_FP64) {
+        WS<double> ws{(double *)iwork, wi, kWsDbl, kWsInt};
+        return run_lu<double, 1>(ctx, sd, 0, ne, (double *)sys, info, ws, false, maxf, 2 * maxf, 2 * maxf + 1, maxf, s);
+    }
+    WS<float> ws{(float *)iwork, wi, kWsDbl, kWsInt};
+    return run_lu<float, 3>(ctx, sd, 0, ne, (float *)sys, info, ws, false, maxf, 2 * maxf, 2 * maxf + 1, maxf, s);
 }
 
 // ---------------------------------------------------------------- mixed path
@@ -1259,8 +1302,8 @@ int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double
     };
     auto forward_solve = [&]() {
         for (int k0 = 0; k0 < maxn; k0 += kNBO) {
-            hipLaunchKernelGGL((k_rowperm<2, 2, float>), rhs_grid, dim3(256), 0, s, dm, sd, e0, k0, 0, 1, M,
-                               block_ws(k0));
+            hipLaunchKernelGGL((k_rowperm<2, 2, float>), dim3((rhs_cols + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm,
+                               sd, e0, k0, 0, 1, M, block_ws(k0));
             rhs_update(true, k0, maxn - k0 - kNBO);
         }
     };

@@ -115,12 +115,13 @@ __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__rest
 // ------------------------------------------------------------- Schwarz setup
 // Systems [[S_r', I], [I, 0]] (row-major, row stride e_ld(m, m)), m = f rounded up to
 // even; for odd f, S_r' = [[S_r, 0], [0, 1]] (one decoupled unknown).
-__global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__restrict__ S, double *__restrict__ sys) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__restrict__ S, T *__restrict__ sys) {
     const int e = blockIdx.y;
     const int *to = dm.toff + 7 * e;
-    const int f = to[6], m = f + (f & 1);
+    const int f = to[6], m = asm_pad(f);
     const int64_t ld = e_ld(m, m);
-    double *base = sys + dm.asmsys_off[e];
+    T *base = sys + dm.asmsys_off[e];
     const int64_t total = (int64_t)2 * m * ld;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(t / ld), c = (int)(t % ld);
@@ -143,30 +144,30 @@ __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__r
         } else if (c < m) {
             v = (c == r - m) ? 1.0 : 0.0;
         }
-        base[t] = v;
+        base[t] = (T)v;
     }
 }
 
-// Sinv (column-major f x f) = -(trailing block), FP64 or FP32
+// Sinv (column-major f x f) = -(trailing block)
 template <typename T>
-__global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const double *__restrict__ sys, T *__restrict__ Sinv) {
+__global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const T *__restrict__ sys, T *__restrict__ Sinv) {
     const int e = blockIdx.z;
-    const int f = dm.toff[7 * e + 6], m = f + (f & 1);
+    const int f = dm.toff[7 * e + 6], m = asm_pad(f);
     const int64_t ld = e_ld(m, m);
     const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
     if (i0 >= f || j0 >= f) return;
-    const double *base = sys + dm.asmsys_off[e];
+    const T *base = sys + dm.asmsys_off[e];
     T *out = Sinv + dm.asm_off[e];
-    __shared__ double tile[32][33];
+    __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = i0 + r, j = j0 + tx;
-        tile[r][tx] = (i < f && j < f) ? -base[(int64_t)(m + i) * ld + m + j] : 0.0;
+        tile[r][tx] = (i < f && j < f) ? -base[(int64_t)(m + i) * ld + m + j] : T(0);
     }
     __syncthreads();
     for (int c = ty; c < 32; c += 8) {
         const int j = j0 + c, i = i0 + tx;
-        if (i < f && j < f) out[(int64_t)j * f + i] = (T)tile[tx][c];
+        if (i < f && j < f) out[(int64_t)j * f + i] = tile[tx][c];
     }
 }
 
@@ -424,18 +425,22 @@ size_t asm_setup_work_bytes(const hdg_ctx *ctx) {
 int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info, void *work,
                      hipStream_t s) {
     const DevMesh &dm = ctx->dm;
-    double *sys = (double *)work;
+    void *sys = work;
     size_t sys_bytes = (sizeof(double) * (size_t)ctx->asmsys_off[ctx->n_elem] + 255) / 256 * 256;
     void *iwork = (void *)((char *)work + sys_bytes);
-    hipLaunchKernelGGL(k_asm_build, dim3(64, ctx->n_elem), dim3(256), 0, s, dm, S, sys);
-    int err = run_asm_inversion(ctx, sys, info, iwork, s);
+    // FP64 inverses for FP64 storage; FP32 storage is inverted in FP32 (FP32 matrix cores)
+    if (prec == HDG_FP64)
+        hipLaunchKernelGGL(k_asm_build<double>, dim3(64, ctx->n_elem), dim3(256), 0, s, dm, S, (double *)sys);
+    else
+        hipLaunchKernelGGL(k_asm_build<float>, dim3(64, ctx->n_elem), dim3(256), 0, s, dm, S, (float *)sys);
+    int err = run_asm_inversion(ctx, prec, sys, info, iwork, s);
     if (err) return err;
     const int maxf = ctx->max_f;
     dim3 grid((maxf + 31) / 32, (maxf + 31) / 32, ctx->n_elem);
     if (prec == HDG_FP64)
         hipLaunchKernelGGL(k_asm_extract<double>, grid, dim3(256), 0, s, dm, (const double *)sys, (double *)Sinv);
     else
-        hipLaunchKernelGGL(k_asm_extract<float>, grid, dim3(256), 0, s, dm, (const double *)sys, (float *)Sinv);
+        hipLaunchKernelGGL(k_asm_extract<float>, grid, dim3(256), 0, s, dm, (const float *)sys, (float *)Sinv);
     return (int)hipGetLastError();
 }
 

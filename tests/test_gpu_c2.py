@@ -134,6 +134,26 @@ def test_mixed_gmres_converged_increment(c0m):
     assert err <= 2.0 * pred + 1e-12 * np.linalg.norm(x)
 
 
+def test_mixed_asm_apply_fp32(c0m):
+    """The Schwarz inverses are computed and stored in FP32 (applied with FP64
+    accumulation): M^{-1} x against the oracle's FP64 LU solves, within the
+    normwise bound of an LU-computed inverse, f cond(S_r) u_32 (largest over
+    the elements' patch matrices)."""
+    import torch
+    st, ts, wl = c0m["st"], c0m["ts"], c0m["wl"]
+    x = torch.as_tensor(wl.x, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(x)
+    work = torch.empty(st.ctx.workspace_size(3), dtype=torch.uint8, device="cuda")
+    st.ctx.hdg_asm_block_apply(1, st.Sinv, x, z, work)
+    torch.cuda.synchronize()
+    err = rel_err(z.cpu().numpy(), ts.asm_apply(wl.x))
+    f = int(st.ctx.layout["elem_f"][0])
+    cond = max(np.linalg.cond(ts.patch_matrix(r)) for r in range(0, wl.mesh.n_elem, 9))
+    bound = f * cond * float(np.finfo(np.float32).eps)
+    print(f"  M^-1 x (FP32 inverses): {err:.3e}; bound f cond(S_r) u32 = {bound:.3e} (cond {cond:.1f})")
+    assert err <= bound
+
+
 def test_mixed_recovery(c0m):
     """d(Q,U) = -(x_r + X_B dUh) inherits X's error; held against the same
     recovery from the LAPACK run of the recipe."""
