@@ -46,6 +46,31 @@ def mixed_flops_per_element(n, f, refine=1):
     return f32, f64
 
 
+def measured_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (profiles/<name>.json), or None when the kernel sources it was taken on
+    have changed since (their SHA-256 no longer matches)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    for src, digest in rec["sources_sha256"].items():
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return rec["bytes_per_launch"]
+
+
+def calibration_copy(torch):
+    """A plain 1 GiB device-to-device copy: the known-size reference that scales
+    the FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    src = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def matvec_bytes(ctx):
     """Algorithmic bytes of y = S x: S read once, block-sparse indices, x read
     once, y written once."""
@@ -217,15 +242,17 @@ def main():
         "condense_elements_per_s": ne / t_cond,
         "phase_ms": phase_ms,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic("condense_fp64_tgv8_p3_hbm"),
                      "kernel": "hdg_condense (per 128-column block: k_panel x2, k_crows, k_rowperm, "
                                "k_update; then k_extract)",
                      "algorithmic": f"{condense_flops_per_element(n, f):.4e} flop/element x {ne} elements"},
         "roofline_matvec": {"bound": "hbm", "achieved": mv_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                            "frac": mv_gbps / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_matvec",
+                            "frac": mv_gbps / PEAK_HBM_GBPS, "traffic": measured_traffic("matvec_tgv8_p3_hbm"),
+                            "kernel": "k_matvec",
                             "ms": mv_ms, "algorithmic_bytes": mv_bytes},
     }
     out["mixed"] = mixed
+    calibration_copy(torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
