@@ -116,6 +116,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1, choices=(1, 4),
+                    help="1: 8^3 p=3 supersonic TGV (the headline workload); 4: 12^3 p=4, chunks of 256, "
+                         "GMRES(50) with FP32 Schwarz, step replayed from a HIP graph")
+    ap.add_argument("--graph", action="store_true", help="also time the step replayed from a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -128,29 +132,29 @@ def main():
     import torch
     from paper_2608_27863_amd import hdg, pipeline, synth
 
-    wl = synth.config(1)
+    big = args.config == 4
+    use_graph = args.graph or big
+    wl = synth.config(args.config)
+    chunk = 256 if big else None
+    asm_fp64 = hdg.HDG_MIXED if big else hdg.HDG_FP64  # the p=4 workload uses FP32 Schwarz blocks throughout
     print(f"[bench] workload {wl.name}: building context", file=sys.stderr, flush=True)
-    st = pipeline.NewtonStep(wl, prec=hdg.HDG_FP64)
+    st = pipeline.NewtonStep(wl, prec=hdg.HDG_FP64, asm_prec=asm_fp64, chunk=chunk)
     ctx = st.ctx
     ne = ctx.n_elem
     n, f = int(ctx.layout["elem_n"][0]), int(ctx.layout["elem_f"][0])
+    p = int(wl.mesh.elem_p[0])
     stream = torch.cuda.current_stream()
     phases = ["residual_jacobian", "condense", "assemble", "asm_setup", "gmres", "recover"]
 
-    def step(events=None):
-        for i, ph in enumerate(phases):
+    def stepper(obj):
+        def step(events=None):
+            for i, ph in enumerate(phases):
+                if events is not None:
+                    events[i].record(stream)
+                getattr(obj, ph)()
             if events is not None:
-                events[i].record(stream)
-            getattr(st, ph)()
-        if events is not None:
-            events[-1].record(stream)
-
-    for w in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    if not np.all(st.info.cpu().numpy() == 0) or not np.all(st.asm_info.cpu().numpy() == 0):
-        raise RuntimeError("zero pivot reported during the warm-up")
+                events[-1].record(stream)
+        return step
 
     def timed(run_step):
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(args.steps)]
@@ -164,47 +168,34 @@ def main():
                     for i, ph in enumerate(phases)}
         return 1e3 * wall / args.steps, phase_ms
 
+    def timed_graph(obj):
+        graph = obj.capture()
+        for _ in range(max(1, args.warmup)):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / args.steps
+
+    def check(obj, what):
+        if not np.all(obj.info.cpu().numpy() == 0) or not np.all(obj.asm_info.cpu().numpy() == 0):
+            raise RuntimeError(f"zero pivot reported in the {what} warm-up")
+
+    step = stepper(st)
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    check(st, "FP64")
     ms_step, phase_ms = timed(step)
     print(f"[bench] {args.steps} timed steps: {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
-    S64, g64, d64 = st.S.clone(), st.g.clone(), st.dUhat.clone()
-
-    # mixed-precision step on the same workload and context
-    stm = pipeline.NewtonStep(wl, prec=hdg.HDG_MIXED, refine_steps=1, ctx=ctx)
-
-    def step_mixed(events=None):
-        for i, ph in enumerate(phases):
-            if events is not None:
-                events[i].record(stream)
-            getattr(stm, ph)()
-        if events is not None:
-            events[-1].record(stream)
-
-    for w in range(args.warmup):
-        step_mixed()
-        torch.cuda.synchronize()
-    if not np.all(stm.info.cpu().numpy() == 0) or not np.all(stm.asm_info.cpu().numpy() == 0):
-        raise RuntimeError("zero pivot reported in the mixed warm-up")
-    ms_mixed, phase_mixed = timed(step_mixed)
-    print(f"[bench] mixed: {ms_mixed:.2f} ms/step", file=sys.stderr, flush=True)
-    relnorm = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
-    f32fl, f64fl = mixed_flops_per_element(n, f, 1)
-    t_cm = phase_mixed["condense"] * 1e-3
-    t_peak = ne * (f32fl / (PEAK_FP32_TFLOPS * 1e12) + f64fl / (PEAK_FP64_TFLOPS * 1e12))
-    mixed = {
-        "value": ne / (ms_mixed * 1e-3), "unit": "elements/s", "ms_per_step": ms_mixed,
-        "condense_elements_per_s": ne / t_cm, "phase_ms": phase_mixed,
-        "refine_steps": 1, "schwarz": "element-block, FP32 inverses",
-        "rel_diff_vs_fp64_step": {"S": relnorm(stm.S, S64), "g": relnorm(stm.g, g64),
-                                  "dUhat_fixed_m": relnorm(stm.dUhat, d64)},
-        "roofline": {"bound": "mfma", "time_at_peak_ms": 1e3 * t_peak, "frac": t_peak / t_cm,
-                     "algorithmic": f"{f32fl:.4e} FP32 + {f64fl:.4e} FP64 flop/element x {ne} elements "
-                                    f"(peaks {PEAK_FP32_TFLOPS} / {PEAK_FP64_TFLOPS} TFLOP/s)"},
-    }
-
-    # condensation roofline (FP64 MFMA): dense algorithmic flops / hdg_condense time
-    fl = condense_flops_per_element(n, f) * ne
-    t_cond = phase_ms["condense"] * 1e-3
-    achieved = fl / t_cond / 1e12
+    graph_ms = timed_graph(st) if use_graph else None
+    if graph_ms is not None:
+        print(f"[bench] graph replay: {graph_ms:.2f} ms/step", file=sys.stderr, flush=True)
+    S64 = None if big else st.S.clone()
+    g64, d64 = st.g.clone(), st.dUhat.clone()
 
     # face matvec roofline (HBM): algorithmic bytes / kernel time, alternating buffers
     x0 = torch.as_tensor(wl.x, dtype=torch.float64, device="cuda")
@@ -223,6 +214,38 @@ def main():
     mv_bytes = matvec_bytes(ctx)
     mv_gbps = mv_bytes / (mv_ms * 1e-3) / 1e9
 
+    # mixed-precision step on the same workload and context
+    stm = pipeline.NewtonStep(wl, prec=hdg.HDG_MIXED, refine_steps=1, ctx=ctx, chunk=chunk,
+                              share=st if big else None)
+    step_mixed = stepper(stm)
+    for w in range(args.warmup):
+        step_mixed()
+        torch.cuda.synchronize()
+    check(stm, "mixed")
+    ms_mixed, phase_mixed = timed(step_mixed)
+    print(f"[bench] mixed: {ms_mixed:.2f} ms/step", file=sys.stderr, flush=True)
+    graph_mixed = timed_graph(stm) if use_graph else None
+    relnorm = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    f32fl, f64fl = mixed_flops_per_element(n, f, 1)
+    t_cm = phase_mixed["condense"] * 1e-3
+    t_peak = ne * (f32fl / (PEAK_FP32_TFLOPS * 1e12) + f64fl / (PEAK_FP64_TFLOPS * 1e12))
+    mixed = {
+        "value": ne / (ms_mixed * 1e-3), "unit": "elements/s", "ms_per_step": ms_mixed,
+        "graph_ms_per_step": graph_mixed,
+        "condense_elements_per_s": ne / t_cm, "phase_ms": phase_mixed,
+        "refine_steps": 1, "schwarz": "element-block, FP32 inverses",
+        "rel_diff_vs_fp64_step": {"S": None if S64 is None else relnorm(stm.S, S64), "g": relnorm(stm.g, g64),
+                                  "dUhat_fixed_m": relnorm(stm.dUhat, d64)},
+        "roofline": {"bound": "mfma", "time_at_peak_ms": 1e3 * t_peak, "frac": t_peak / t_cm,
+                     "algorithmic": f"{f32fl:.4e} FP32 + {f64fl:.4e} FP64 flop/element x {ne} elements "
+                                    f"(peaks {PEAK_FP32_TFLOPS} / {PEAK_FP64_TFLOPS} TFLOP/s)"},
+    }
+
+    # condensation roofline (FP64 matrix cores): dense algorithmic flops / hdg_condense time
+    fl = condense_flops_per_element(n, f) * ne
+    t_cond = phase_ms["condense"] * 1e-3
+    achieved = fl / t_cond / 1e12
+    tag = "tgv8_p3" if not big else "tgv12_p4"
     out = {
         "metric": "HDG condensed elements/s, FP64 vs mixed @1e-10 rel; face-matvec GB/s",
         "value": ne / (ms_step * 1e-3),
@@ -236,22 +259,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "elements": ne, "p": 3, "n_interior": n, "f_trace": f,
-                   "gmres_iterations": st.m, "schwarz": "element-block, FP64", "precision": "FP64",
-                   "step": "residual+Jacobian, condensation, assembly, Schwarz set-up, GMRES(30), recovery"},
+        "config": {"workload": wl.name, "elements": ne, "p": p, "n_interior": n, "f_trace": f,
+                   "chunk": chunk or ne, "gmres_iterations": st.m,
+                   "schwarz": "element-block, " + ("FP32 inverses" if big else "FP64"), "precision": "FP64",
+                   "step": f"residual+Jacobian, condensation, assembly, Schwarz set-up, GMRES({st.m}), recovery"},
+        "graph_ms_per_step": graph_ms,
         "condense_elements_per_s": ne / t_cond,
         "phase_ms": phase_ms,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic("condense_fp64_tgv8_p3_hbm"),
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(f"condense_fp64_{tag}_hbm"),
                      "kernel": "hdg_condense (per 128-column block: k_panel x2, k_crows, k_rowperm, "
                                "k_update; then k_extract)",
                      "algorithmic": f"{condense_flops_per_element(n, f):.4e} flop/element x {ne} elements"},
         "roofline_matvec": {"bound": "hbm", "achieved": mv_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                            "frac": mv_gbps / PEAK_HBM_GBPS, "traffic": measured_traffic("matvec_tgv8_p3_hbm"),
-                            "kernel": "k_matvec",
-                            "ms": mv_ms, "algorithmic_bytes": mv_bytes},
+                            "frac": mv_gbps / PEAK_HBM_GBPS, "traffic": measured_traffic(f"matvec_{tag}_hbm"),
+                            "kernel": "k_matvec", "ms": mv_ms, "algorithmic_bytes": mv_bytes},
+        "mixed": mixed,
     }
-    out["mixed"] = mixed
     calibration_copy(torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)

@@ -507,7 +507,7 @@ int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, siz
             *bytes = (prec == HDG_FP64) ? round256(hdg::bordered_lu_work(ctx, ne))
                                         : hdg::condense_mixed_work_bytes(ctx, e0, ne);
             return HDG_OK;
-        case 2: *bytes = hdg::asm_setup_work_bytes(ctx); return HDG_OK;
+        case 2: *bytes = hdg::asm_setup_work_bytes(ctx, prec); return HDG_OK;
         case 3: *bytes = hdg::asm_apply_work_bytes(ctx); return HDG_OK;
         case 4:
             if (ne < 1 || ne > 200) return HDG_ERR_INVALID_ARGUMENT;
@@ -560,7 +560,7 @@ int hdg_asm_setup(hdg_ctx *ctx, int prec, const double *S_bsr, void *Sinv, int *
                   size_t work_bytes, void *stream) {
     if (!ctx || !S_bsr || !Sinv || !info || (prec != HDG_FP64 && prec != HDG_MIXED)) return HDG_ERR_INVALID_ARGUMENT;
     if (ctx->repeated_face) return HDG_ERR_UNSUPPORTED;
-    if (work_bytes < hdg::asm_setup_work_bytes(ctx) || !work) return HDG_ERR_WORKSPACE;
+    if (work_bytes < hdg::asm_setup_work_bytes(ctx, prec) || !work) return HDG_ERR_WORKSPACE;
     return dev_status(hdg::launch_asm_setup(ctx, prec, S_bsr, Sinv, info, work, (hipStream_t)stream));
 }
 

@@ -118,7 +118,7 @@ int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, 
 int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *y, hipStream_t s);
 int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info,
                      void *work, hipStream_t s);
-size_t asm_setup_work_bytes(const hdg_ctx *ctx);
+size_t asm_setup_work_bytes(const hdg_ctx *ctx, int prec);
 int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
                      void *work, hipStream_t s);
 size_t asm_apply_work_bytes(const hdg_ctx *ctx);

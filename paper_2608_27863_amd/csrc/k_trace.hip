@@ -416,8 +416,9 @@ int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *
     return (int)hipGetLastError();
 }
 
-size_t asm_setup_work_bytes(const hdg_ctx *ctx) {
-    size_t sys = sizeof(double) * (size_t)ctx->asmsys_off[ctx->n_elem];
+size_t asm_setup_work_bytes(const hdg_ctx *ctx, int prec) {
+    const size_t es = (prec == HDG_FP64) ? sizeof(double) : sizeof(float);
+    size_t sys = es * (size_t)ctx->asmsys_off[ctx->n_elem];
     size_t iw = bordered_lu_work(ctx, ctx->n_elem);
     return (sys + 255) / 256 * 256 + (iw + 255) / 256 * 256;
 }
@@ -426,7 +427,8 @@ int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, 
                      hipStream_t s) {
     const DevMesh &dm = ctx->dm;
     void *sys = work;
-    size_t sys_bytes = (sizeof(double) * (size_t)ctx->asmsys_off[ctx->n_elem] + 255) / 256 * 256;
+    const size_t es = (prec == HDG_FP64) ? sizeof(double) : sizeof(float);
+    size_t sys_bytes = (es * (size_t)ctx->asmsys_off[ctx->n_elem] + 255) / 256 * 256;
     void *iwork = (void *)((char *)work + sys_bytes);
     // FP64 inverses for FP64 storage; FP32 storage is inverted in FP32 (FP32 matrix cores)
     if (prec == HDG_FP64)

@@ -14,7 +14,10 @@ from .hdg import HDG_FP64, HDG_MIXED, Context
 
 class NewtonStep:
     def __init__(self, wl, prec=HDG_FP64, refine_steps=1, asm_prec=None, chunk=None, m=None,
-                 ctx=None, device="cuda"):
+                 ctx=None, device="cuda", share=None):
+        """share: another NewtonStep on the same context whose device buffers are
+        reused where shape and type agree (the two steps then overwrite each
+        other's results; useful when the element systems are large)."""
         import torch
         self.wl = wl
         self.prec = prec
@@ -27,26 +30,36 @@ class NewtonStep:
         self.chunk = ne if chunk is None else int(chunk)
         self.chunks = [(e0, min(self.chunk, ne - e0)) for e0 in range(0, ne, self.chunk)]
         f64 = dict(dtype=torch.float64, device=device)
-        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), **f64)
-        self.Q, self.U, self.Un = t(wl.Q), t(wl.U), t(wl.Un)
-        self.Uhat, self.nu, self.Ub = t(wl.Uhat), t(wl.nu), t(wl.Ub)
-        self.E = torch.empty(int(c.layout["E_off"][-1]), **f64)
+
+        def buf(name, numel, dtype=torch.float64, zero=False):
+            old = getattr(share, name, None) if share is not None else None
+            if old is not None and old.dtype == dtype and old.numel() >= numel:
+                return old
+            return (torch.zeros if zero else torch.empty)(numel, dtype=dtype, device=device)
+
+        def inp(name, a):
+            old = getattr(share, name, None) if share is not None else None
+            return old if old is not None else torch.as_tensor(np.ascontiguousarray(a), **f64)
+
+        self.Q, self.U, self.Un = inp("Q", wl.Q), inp("U", wl.U), inp("Un", wl.Un)
+        self.Uhat, self.nu, self.Ub = inp("Uhat", wl.Uhat), inp("nu", wl.nu), inp("Ub", wl.Ub)
+        self.E = buf("E", int(c.layout["E_off"][-1]))
         qp = max(c.workspace_size(0, HDG_FP64, e0, n) for e0, n in self.chunks)
-        self.qp_work = torch.empty(qp, dtype=torch.uint8, device=device)
+        self.qp_work = buf("qp_work", qp, torch.uint8)
         cw = max(c.workspace_size(1, prec, e0, n) for e0, n in self.chunks)
-        self.cond_work = torch.empty(cw, dtype=torch.uint8, device=device)
-        self.SK = torch.empty(int(c.layout["SK_off"][-1]), **f64)
-        self.info = torch.zeros(ne, dtype=torch.int32, device=device)
-        self.S = torch.empty(int(c.layout["bsr_val_off"][-1]), **f64)
-        self.g = torch.empty(c.N_uh, **f64)
+        self.cond_work = buf("cond_work", cw, torch.uint8)
+        self.SK = buf("SK", int(c.layout["SK_off"][-1]))
+        self.info = buf("info", ne, torch.int32, zero=True)
+        self.S = buf("S", int(c.layout["bsr_val_off"][-1]))
+        self.g = buf("g", c.N_uh)
         sdt = torch.float64 if self.asm_prec == HDG_FP64 else torch.float32
-        self.Sinv = torch.empty(int(c.layout["asm_off"][-1]), dtype=sdt, device=device)
-        self.asm_info = torch.zeros(ne, dtype=torch.int32, device=device)
-        self.asm_work = torch.empty(c.workspace_size(2, self.asm_prec), dtype=torch.uint8, device=device)
-        self.gm_work = torch.empty(c.workspace_size(4, self.asm_prec, 0, self.m), dtype=torch.uint8, device=device)
-        self.dUhat = torch.empty(c.N_uh, **f64)
+        self.Sinv = buf("Sinv", int(c.layout["asm_off"][-1]), sdt)
+        self.asm_info = buf("asm_info", ne, torch.int32, zero=True)
+        self.asm_work = buf("asm_work", c.workspace_size(2, self.asm_prec), torch.uint8)
+        self.gm_work = buf("gm_work", c.workspace_size(4, self.asm_prec, 0, self.m), torch.uint8)
+        self.dUhat = buf("dUhat", c.N_uh)
         self.hist = torch.empty(self.m + 1, **f64)
-        self.dQU = torch.empty(20 * int(c.layout["node_off"][-1]), **f64)
+        self.dQU = buf("dQU", 20 * int(c.layout["node_off"][-1]))
 
     def E_chunk(self, e0, n):
         o = self.ctx.layout["E_off"]
@@ -86,3 +99,16 @@ class NewtonStep:
         self.asm_setup(stream)
         self.gmres(stream)
         self.recover(stream)
+
+    def capture(self):
+        """The whole Newton step captured once in a HIP graph (torch.cuda.CUDAGraph).
+        Every launch of the step goes to the capturing stream; nothing is
+        allocated or synchronised inside.  graph.replay() reruns the step on the
+        current contents of the input buffers."""
+        import torch
+        self.run()  # first launches outside the capture (lazy loading of the code objects)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.run()
+        return graph
