@@ -8,9 +8,11 @@
 //       av-total and the numerical flux of eq. num-flux-hdg, and their exact
 //       Jacobians (derived by hand below), already multiplied by quadrature
 //       weights, the geometric factors and dt / alpha;
-//   k_assemble_rows : contract the point coefficients with the basis
-//       (phi_i, reference derivatives of phi_i, phi_k, trace basis mu_a) into
-//       the rows of the element system E^K = [[A B R_qu],[C D R_uh]].
+//   k_assemble_field_rows / k_assemble_trace_rows : contract the point
+//       coefficients with the basis (phi_i, reference derivatives of phi_i,
+//       phi_k, trace basis mu_a) into the rows of the element system
+//       E^K = [[A B R_qu],[C D R_uh]], by sum factorisation over the tensor
+//       Gauss points.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -324,17 +326,11 @@ __device__ inline bool on_face(int i, int p1, int lf, int &a0, int &a1) {
     return true;
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kKC = 32;       // quadrature points per LDS chunk
 
-// Shared set-up of the element-row kernels: 1-D tables of the element and of
-// its faces, face quadrature bases in the point workspace.
-struct RowSetup {
-    int p, p1, Np, nq, Nq, n, f;
-    int64_t ld;
-};
-
+// Face tables of the element-row kernels: the element's 1-D basis and each
+// face's trace basis at the face's Gauss points, face quadrature bases in the
+// point workspace.
 __device__ inline void load_face_tables(const DevMesh &dm, int e, int p, int Nq, double (*sLf)[30],
                                         double (*sMf)[30], int *sPf, int *sNqf, int64_t *sFbase) {
     const int tid = threadIdx.x;
@@ -353,239 +349,230 @@ __device__ inline void load_face_tables(const DevMesh &dm, int e, int p, int Nq,
     }
 }
 
-// Interior rows of the element system.  blockIdx.x: 0..2 = gradient rows of
-// direction j (fields 3c+j, c = 0..4: the mass block and the block
-// int phi_k d_j phi_i are the same for every c), 3..7 = conservation rows of
-// component c.  Each Np x Np block is sum_g phi_k(g) [c0 phi_i + c_d dref_d phi_i](g),
-// formed with FP64 MFMA from LDS chunks of the point coefficients.
-template <int T>
-__global__ void __launch_bounds__(256) k_assemble_interior(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
-                                                           double *__restrict__ Ebase) {
-    constexpr int RB = (T >= 4) ? T / 4 : 1;  // 16-row blocks per wave
-    constexpr int CB = (T >= 4) ? T : 1;      // 16-column blocks per wave
-    constexpr int KC = (T == 8) ? 16 : kKC;   // quadrature points per chunk
-    constexpr int HS = KC + 2;                // LDS row stride
-    constexpr int NR = 16 * T;                // padded basis count
-    const int e = e0 + blockIdx.y, rb = blockIdx.x;
+// Interior rows of one row field r of the element system, one workgroup per
+// (field, element): the 20 column blocks of A, the trace columns B, the residual
+// column and the padding, all written.  Gradient rows r = 3c+j hold the mass
+// block (column field r) and K_j = int phi_k d_j phi_i (column field 15+c) and
+// zeros elsewhere; conservation rows r = 15+c hold the blocks of the point
+// Jacobians plus their face terms.
+//
+// Every N_p x N_p block sum_g phi_k(g) [c0 phi_i + sum_d c_d dref_d phi_i](g) is
+// contracted one direction at a time over the tensor Gauss points (sum
+// factorisation), one i1 slice at a time:
+//   x:  T0 = sum_g1 (L_i1 c0 + D_i1 c1) L_k1,  T2 = sum_g1 L_i1 c2 L_k1,  T3 = sum_g1 L_i1 c3 L_k1
+//   y:  VL = sum_g2 (L_i2 T0 + D_i2 T2) L_k2,   VD = sum_g2 L_i2 T3 L_k2
+//   z:  A  = sum_g3 (L_i3 VL + D_i3 VD) L_k3
+// (L, D: the 1-D basis and its derivative at the Gauss points).  The face terms
+// and the trace columns are 2-D contractions over each face's Gauss points.
+constexpr int kP1 = kMaxP + 1, kNQ = kMaxP + 2;
+constexpr int kNqMax = kNQ * kNQ * kNQ;
+
+__global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
+                                                             double *__restrict__ Ebase) {
+    const int r = blockIdx.x, e = e0 + blockIdx.y;
     const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
     const int *toff = dm.toff + 7 * e;
     const int n = 20 * Np, f = toff[6];
     const int64_t ld = e_ld(n, f);
     double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    double *Er = E + (int64_t)r * Np * ld;
     const double *qpe = qp + (dm.qp_off[e] - dm.qp_off[e0]);
     const double *vg = dm.vgeo + dm.vgeo_off[e];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool qrows = rb < 3;
-    const int jdir = qrows ? rb : 0, cu = qrows ? 0 : rb - 3;
+    const int tid = threadIdx.x;
+    const bool qrow = r < 15;
+    const int c = qrow ? r / 3 : r - 15, jdir = qrow ? r % 3 : 0;
 
-    __shared__ double sL[30], sD[30];
+    __shared__ double sL[kP1][kNQ], sD[kP1][kNQ];
     __shared__ double sLf[6][30], sMf[6][30];
     __shared__ int sPf[6], sNqf[6];
     __shared__ int64_t sFbase[6];
-    __shared__ unsigned short s_ix[128], s_gx[216];
-    __shared__ double sH[NR][HS], sP[NR][HS];
-    __shared__ double sC[4][KC];
-    __shared__ double sFc[6 * 36];
-    __shared__ double sFB[6 * 5 * 36];
+    __shared__ double sC[4][kNqMax];                        // coefficient fields of one block
+    __shared__ double sT[3][kP1][kNQ * kNQ];                // x stage of one i1 slice
+    __shared__ double sV[2][kP1 * kP1 * kP1][kNQ];          // y stage of one i1 slice
+    __shared__ double sF[6 * kP1 * kP1 * kP1 * kP1];        // face terms / trace-column blocks
+    __shared__ double sG[6 * kP1 * kP1 * kNQ];              // first stage of the 2-D contractions
     for (int t = tid; t < p1 * nq; t += blockDim.x) {
-        sL[t] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
-        sD[t] = dm.tbl[tbl_D(p, t / nq, t % nq)];
+        sL[t / nq][t % nq] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
+        sD[t / nq][t % nq] = dm.tbl[tbl_D(p, t / nq, t % nq)];
     }
-    for (int t = tid; t < Np; t += blockDim.x) s_ix[t] = (unsigned short)((t % p1) | (((t / p1) % p1) << 4) | ((t / (p1 * p1)) << 8));
-    for (int t = tid; t < Nq; t += blockDim.x) s_gx[t] = (unsigned short)((t % nq) | (((t / nq) % nq) << 4) | ((t / (nq * nq)) << 8));
     load_face_tables(dm, e, p, Nq, sLf, sMf, sPf, sNqf, sFbase);
     __syncthreads();
 
-    auto on_face_ix = [&](int i, int lf, int &a0, int &a1) {
-        const int code = s_ix[i];
-        const int idx[3] = {code & 15, (code >> 4) & 15, code >> 8};
-        const int d = lf >> 1;
-        if (idx[d] != ((lf & 1) ? p : 0)) return false;
-        a0 = idx[d == 0 ? 1 : 0];
-        a1 = idx[d == 2 ? 1 : 2];
+    // face-tangential indices (a0, a1) of volume node (i1, i2, i3) on face lf, or false
+    auto face_idx = [&](int i1, int i2, int i3, int lf, int &a0, int &a1) {
+        const int d = lf >> 1, v = (lf & 1) ? p : 0;
+        const int id = (d == 0) ? i1 : ((d == 1) ? i2 : i3);
+        if (id != v) return false;
+        a0 = (d == 0) ? i2 : i1;
+        a1 = (d == 2) ? i2 : i3;
         return true;
     };
-    auto phi_face = [&](int lf, int a0, int a1, int s) {
-        const int nqf1 = sPf[lf] + 2;
-        return sLf[lf][a0 * nqf1 + (s % nqf1)] * sLf[lf][a1 * nqf1 + (s / nqf1)];
-    };
-    auto mu_face = [&](int lf, int b, int s) {
-        const int pf1 = sPf[lf] + 1, nqf1 = sPf[lf] + 2;
-        return sMf[lf][(b % pf1) * nqf1 + (s % nqf1)] * sMf[lf][(b / pf1) * nqf1 + (s / nqf1)];
-    };
 
-    d4 acc[RB][CB];
-    // kind: 0 = mass (W), 1 = int phi_k d_j phi_i (W G[d][j]), 2 = conservation row cu, column field sblk
-    auto block_product = [&](int kind, int sblk) {
-#pragma unroll
-        for (int a = 0; a < RB; ++a)
-#pragma unroll
-            for (int b = 0; b < CB; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
-        for (int g0 = 0; g0 < Nq; g0 += KC) {
+    // one sum-factorised block from sC into column field sblk (with the face terms in sF)
+    auto volume_block = [&](int sblk, bool faces) {
+        for (int i1 = 0; i1 < p1; ++i1) {
             __syncthreads();
-            if (tid < 4 * KC) {
-                const int d = tid / KC, gg = tid % KC, g = g0 + gg;
+            for (int t = tid; t < p1 * nq * nq; t += blockDim.x) {
+                const int k1 = t / (nq * nq), g23 = t % (nq * nq);
+                double a0 = 0.0, a2 = 0.0, a3 = 0.0;
+                for (int g1 = 0; g1 < nq; ++g1) {
+                    const int g = g1 + nq * g23;
+                    const double lk = sL[k1][g1], li = sL[i1][g1];
+                    a0 += (li * sC[0][g] + sD[i1][g1] * sC[1][g]) * lk;
+                    a2 += li * sC[2][g] * lk;
+                    a3 += li * sC[3][g] * lk;
+                }
+                sT[0][k1][g23] = a0;
+                sT[1][k1][g23] = a2;
+                sT[2][k1][g23] = a3;
+            }
+            __syncthreads();
+            for (int t = tid; t < p1 * p1 * p1 * nq; t += blockDim.x) {
+                const int g3 = t % nq, q = t / nq;  // q = (i2 p1 + k1) p1 + k2
+                const int k2 = q % p1, k1 = (q / p1) % p1, i2 = q / (p1 * p1);
+                double vl = 0.0, vd = 0.0;
+                for (int g2 = 0; g2 < nq; ++g2) {
+                    const int g23 = g2 + nq * g3;
+                    const double lk = sL[k2][g2];
+                    vl += (sL[i2][g2] * sT[0][k1][g23] + sD[i2][g2] * sT[1][k1][g23]) * lk;
+                    vd += sL[i2][g2] * sT[2][k1][g23] * lk;
+                }
+                sV[0][q][g3] = vl;
+                sV[1][q][g3] = vd;
+            }
+            __syncthreads();
+            for (int t = tid; t < p1 * p1 * Np; t += blockDim.x) {
+                const int k = t % Np, q = t / Np;
+                const int i2 = q % p1, i3 = q / p1;
+                const int k1 = k % p1, k2 = (k / p1) % p1, k3 = k / (p1 * p1);
+                const int vq = (i2 * p1 + k1) * p1 + k2;
                 double v = 0.0;
-                if (g < Nq) {
-                    if (kind == 0) v = (d == 0) ? vg[g] : 0.0;
-                    else if (kind == 1) v = (d == 0) ? 0.0 : vg[g] * vg[(1 + 3 * (d - 1) + jdir) * Nq + g];
-                    else v = qpe[(int64_t)(4 * (20 * cu + sblk) + d) * Nq + g];
-                }
-                sC[d][gg] = v;
-            }
-            __syncthreads();
-#pragma unroll 4
-            for (int q = 0; q < (NR * KC + 255) / 256; ++q) {
-                const int t = tid + 256 * q;
-                if (t >= NR * KC) break;
-                const int i = t / KC, gg = t % KC, g = g0 + gg;
-                double h = 0.0, ph = 0.0;
-                if (i < Np && g < Nq) {
-                    const int ci = s_ix[i], cg = s_gx[g];
-                    const int a0 = (ci & 15) * nq + (cg & 15), a1 = ((ci >> 4) & 15) * nq + ((cg >> 4) & 15),
-                              a2 = (ci >> 8) * nq + (cg >> 8);
-                    const double l0 = sL[a0], l1 = sL[a1], l2 = sL[a2];
-                    ph = l0 * l1 * l2;
-                    h = sC[0][gg] * ph + sC[1][gg] * sD[a0] * l1 * l2 + sC[2][gg] * l0 * sD[a1] * l2 +
-                        sC[3][gg] * l0 * l1 * sD[a2];
-                }
-                sH[i][gg] = h;
-                sP[i][gg] = ph;
-            }
-            __syncthreads();
-            if (T >= 2 || wave == 0) {
-#pragma unroll
-                for (int kk = 0; kk < KC; kk += 4) {
-                    double av[RB];
-#pragma unroll
-                    for (int a = 0; a < RB; ++a) {
-                        const int bi = (T >= 4) ? wave * RB + a : ((T == 2) ? (wave >> 1) : 0);
-                        av[a] = sH[16 * bi + (lane & 15)][kk + (lane >> 4)];
-                    }
-#pragma unroll
-                    for (int b = 0; b < CB; ++b) {
-                        const int bj = (T >= 4) ? b : ((T == 2) ? (wave & 1) : 0);
-                        const double bv = sP[16 * bj + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-                        for (int a = 0; a < RB; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv, acc[a][b], 0, 0, 0);
+                for (int g3 = 0; g3 < nq; ++g3)
+                    v += (sL[i3][g3] * sV[0][vq][g3] + sD[i3][g3] * sV[1][vq][g3]) * sL[k3][g3];
+                if (faces) {
+                    for (int lf = 0; lf < 6; ++lf) {
+                        int a0, a1, b0, b1;
+                        if (face_idx(i1, i2, i3, lf, a0, a1) && face_idx(k1, k2, k3, lf, b0, b1))
+                            v += sF[lf * p1 * p1 * p1 * p1 + ((a0 * p1 + a1) * p1 + b0) * p1 + b1];
                     }
                 }
+                Er[(int64_t)(i1 + p1 * q) * ld + sblk * Np + k] = v;
             }
         }
-    };
-    // write the block (plus face terms of the conservation rows) to rows of field r
-    auto write_block = [&](int r, int sblk, bool faces) {
-        if (!(T >= 2 || wave == 0)) return;
-#pragma unroll
-        for (int a = 0; a < RB; ++a)
-#pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                const int bi = (T >= 4) ? wave * RB + a : ((T == 2) ? (wave >> 1) : 0);
-                const int bj = (T >= 4) ? b : ((T == 2) ? (wave & 1) : 0);
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int i = 16 * bi + 4 * jj + (lane >> 4), k = 16 * bj + (lane & 15);
-                    if (i >= Np || k >= Np) continue;
-                    double v = acc[a][b][jj];
-                    if (faces) {
-                        for (int lf = 0; lf < 6; ++lf) {
-                            int ia0, ia1, ka0, ka1;
-                            if (!on_face_ix(i, lf, ia0, ia1) || !on_face_ix(k, lf, ka0, ka1)) continue;
-                            for (int s = 0; s < sNqf[lf]; ++s)
-                                v += sFc[lf * 36 + s] * phi_face(lf, ia0, ia1, s) * phi_face(lf, ka0, ka1, s);
-                        }
-                    }
-                    E[(int64_t)(r * Np + i) * ld + sblk * Np + k] = v;
-                }
-            }
-    };
-    auto zero_block = [&](int r, int sblk) {
-        for (int t = tid; t < Np * Np; t += blockDim.x) E[(int64_t)(r * Np + t / Np) * ld + sblk * Np + t % Np] = 0.0;
     };
 
-    if (qrows) {
-        // mass blocks on the diagonal of every gradient row field of direction jdir
-        block_product(0, 0);
-        for (int c = 0; c < 5; ++c) write_block(3 * c + jdir, 3 * c + jdir, false);
-        block_product(1, 0);
-        for (int c = 0; c < 5; ++c) write_block(3 * c + jdir, 15 + c, false);
-        for (int c = 0; c < 5; ++c) {
-            const int r = 3 * c + jdir;
-            for (int sblk = 0; sblk < 20; ++sblk)
-                if (sblk != r && sblk != 15 + c) zero_block(r, sblk);
-        }
-    } else {
-        const int slotbase = 0;
-        (void)slotbase;
-        for (int sblk = 0; sblk < 20; ++sblk) {
+    if (qrow) {
+        // mass block and K_j (identical for every component c); zeros elsewhere
+        for (int kind = 0; kind < 2; ++kind) {
             __syncthreads();
-            const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
-            for (int t = tid; t < 6 * 36; t += blockDim.x) {
-                const int lf = t / 36, s = t % 36;
-                sFc[t] = (s < sNqf[lf]) ? P.dt * qpe[sFbase[lf] + (int64_t)(25 * cu + slot) * sNqf[lf] + s] : 0.0;
+            for (int t = tid; t < 4 * Nq; t += blockDim.x) {
+                const int d = t / Nq, g = t % Nq;
+                double v;
+                if (kind == 0) v = (d == 0) ? vg[g] : 0.0;
+                else v = (d == 0) ? 0.0 : vg[g] * vg[(1 + 3 * (d - 1) + jdir) * Nq + g];
+                sC[d][g] = v;
             }
-            block_product(2, sblk);
-            write_block(15 + cu, sblk, true);
+            volume_block(kind == 0 ? r : 15 + c, false);
+        }
+        const int z0 = r * Np, z1 = (15 + c) * Np;
+        for (int i = 0; i < Np; ++i)
+            for (int col = tid; col < n; col += blockDim.x)
+                if ((col < z0 || col >= z0 + Np) && (col < z1 || col >= z1 + Np)) Er[(int64_t)i * ld + col] = 0.0;
+    } else {
+        for (int sblk = 0; sblk < 20; ++sblk) {
+            const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
+            __syncthreads();
+            for (int t = tid; t < 4 * Nq; t += blockDim.x)
+                sC[t / Nq][t % Nq] = qpe[(int64_t)(4 * (20 * c + sblk) + t / Nq) * Nq + t % Nq];
+            // face terms: F[a0 a1][b0 b1] = sum_s c(s) phi_a(s) phi_b(s) per face, two 1-D stages
+            for (int t = tid; t < 6 * p1 * p1 * kNQ; t += blockDim.x) {
+                const int lf = t / (p1 * p1 * kNQ), rem = t % (p1 * p1 * kNQ);
+                const int a0 = rem / (p1 * kNQ), b0 = (rem / kNQ) % p1, s1 = rem % kNQ;
+                const int nqf1 = sPf[lf] + 2;
+                double v = 0.0;
+                if (s1 < nqf1) {
+                    const double *cf = qpe + sFbase[lf] + (int64_t)(25 * c + slot) * sNqf[lf];
+                    for (int s0 = 0; s0 < nqf1; ++s0)
+                        v += sLf[lf][a0 * nqf1 + s0] * sLf[lf][b0 * nqf1 + s0] * cf[s0 + nqf1 * s1];
+                }
+                sG[t] = P.dt * v;
+            }
+            __syncthreads();
+            for (int t = tid; t < 6 * p1 * p1 * p1 * p1; t += blockDim.x) {
+                const int lf = t / (p1 * p1 * p1 * p1), rem = t % (p1 * p1 * p1 * p1);
+                const int b1 = rem % p1, b0 = (rem / p1) % p1, a1 = (rem / (p1 * p1)) % p1, a0 = rem / (p1 * p1 * p1);
+                const int nqf1 = sPf[lf] + 2;
+                const double *gg = sG + lf * p1 * p1 * kNQ + (a0 * p1 + b0) * kNQ;
+                double v = 0.0;
+                for (int s1 = 0; s1 < nqf1; ++s1) v += sLf[lf][a1 * nqf1 + s1] * sLf[lf][b1 * nqf1 + s1] * gg[s1];
+                sF[t] = v;
+            }
+            volume_block(sblk, true);
         }
     }
-    // ---- B columns (face lf, component cp, trace node b) and residual/padding columns
-    const int nfield = qrows ? 5 : 1;
-    for (int fi = 0; fi < nfield; ++fi) {
-        const int c = qrows ? fi : cu;
-        const int r = qrows ? 3 * fi + jdir : 15 + cu;
+    // ---- trace columns B: face by face, B_lf[cp][a0 a1][b0 b1] = sum_s c_cp(s) phi_a(s) mu_b(s)
+    for (int lf = 0; lf < 6; ++lf) {
+        const int pf1 = sPf[lf] + 1, nqf1 = sPf[lf] + 2, Nqf = sNqf[lf], Nfp = pf1 * pf1;
         __syncthreads();
-        for (int t = tid; t < 6 * 5 * 36; t += blockDim.x) {
-            const int lf = t / 180, cp = (t / 36) % 5, s = t % 36;
+        for (int t = tid; t < 5 * p1 * pf1 * nqf1; t += blockDim.x) {
+            const int cp = t / (p1 * pf1 * nqf1), rem = t % (p1 * pf1 * nqf1);
+            const int a0 = rem / (pf1 * nqf1), b0 = (rem / nqf1) % pf1, s1 = rem % nqf1;
             double v = 0.0;
-            if (s < sNqf[lf]) {
-                if (qrows) v = (cp == c) ? -dm.fgeo[dm.fgeo_off[6 * e + lf] + (int64_t)jdir * sNqf[lf] + s] : 0.0;
-                else v = P.dt * qpe[sFbase[lf] + (int64_t)(25 * c + 20 + cp) * sNqf[lf] + s];
+            if (!qrow || cp == c) {
+                const double *cf = qrow ? dm.fgeo + dm.fgeo_off[6 * e + lf] + (int64_t)jdir * Nqf
+                                        : qpe + sFbase[lf] + (int64_t)(25 * c + 20 + cp) * Nqf;
+                for (int s0 = 0; s0 < nqf1; ++s0)
+                    v += sLf[lf][a0 * nqf1 + s0] * sMf[lf][b0 * nqf1 + s0] * cf[s0 + nqf1 * s1];
+                v *= qrow ? -1.0 : P.dt;
             }
-            sFB[t] = v;
+            sG[t] = v;
         }
         __syncthreads();
-        double *Er = E + (int64_t)r * Np * ld;
-        for (int t = tid; t < Np * f; t += blockDim.x) {
-            const int i = t / f, col = t % f;
-            int lf = 0;
-            while (col >= toff[lf + 1]) ++lf;
-            const int pf1 = sPf[lf] + 1, Nfp = pf1 * pf1;
-            const int cp = (col - toff[lf]) / Nfp, b = (col - toff[lf]) % Nfp;
+        for (int t = tid; t < 5 * p1 * p1 * Nfp; t += blockDim.x) {
+            const int cp = t / (p1 * p1 * Nfp), rem = t % (p1 * p1 * Nfp);
+            const int a = rem / Nfp, b = rem % Nfp;
+            const int a0 = a / p1, a1 = a % p1, b0 = b % pf1, b1 = b / pf1;
+            const double *gg = sG + (cp * p1 * pf1 + a0 * pf1 + b0) * nqf1;
             double v = 0.0;
+            for (int s1 = 0; s1 < nqf1; ++s1) v += sLf[lf][a1 * nqf1 + s1] * sMf[lf][b1 * nqf1 + s1] * gg[s1];
+            sF[t] = v;
+        }
+        __syncthreads();
+        const int ncol = 5 * Nfp;
+        for (int t = tid; t < Np * ncol; t += blockDim.x) {
+            const int i = t / ncol, col = t % ncol;
+            const int cp = col / Nfp, b = col % Nfp;
+            const int i1 = i % p1, i2 = (i / p1) % p1, i3 = i / (p1 * p1);
             int a0, a1;
-            if ((!qrows || cp == c) && on_face_ix(i, lf, a0, a1)) {
-                const double *cf = sFB + (lf * 5 + cp) * 36;
-                for (int s = 0; s < sNqf[lf]; ++s) v += cf[s] * phi_face(lf, a0, a1, s) * mu_face(lf, b, s);
-            }
-            Er[(int64_t)i * ld + n + col] = v;
+            const double v = face_idx(i1, i2, i3, lf, a0, a1) ? sF[(cp * p1 * p1 + a0 * p1 + a1) * Nfp + b] : 0.0;
+            Er[(int64_t)i * ld + n + toff[lf] + col] = v;
         }
-        for (int i = tid; i < Np; i += blockDim.x) {
-            double v = 0.0;
-            const double *rc = qpe + (int64_t)kVJac * Nq + (int64_t)(4 * r) * Nq;
-            const int ci = s_ix[i];
-            for (int g = 0; g < Nq; ++g) {
-                const int cg = s_gx[g];
-                const int a0 = (ci & 15) * nq + (cg & 15), a1 = ((ci >> 4) & 15) * nq + ((cg >> 4) & 15),
-                          a2 = (ci >> 8) * nq + (cg >> 8);
-                const double l0 = sL[a0], l1 = sL[a1], l2 = sL[a2];
-                v += rc[g] * l0 * l1 * l2 + rc[Nq + g] * sD[a0] * l1 * l2 + rc[2 * Nq + g] * l0 * sD[a1] * l2 +
-                     rc[3 * Nq + g] * l0 * l1 * sD[a2];
-            }
-            for (int lf = 0; lf < 6; ++lf) {
-                int a0, a1;
-                if (!on_face_ix(i, lf, a0, a1)) continue;
-                const int Nqf = sNqf[lf];
-                const double *fb = qpe + sFbase[lf];
-                const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
-                for (int s = 0; s < Nqf; ++s) {
-                    const double ph = phi_face(lf, a0, a1, s);
-                    if (qrows) v -= fgl[jdir * Nqf + s] * fb[(135 + c) * Nqf + s] * ph;
-                    else v += P.dt * fb[(125 + c) * Nqf + s] * ph;
-                }
-            }
-            Er[(int64_t)i * ld + n + f] = v;
-            for (int64_t col = n + f + 1; col < ld; ++col) Er[(int64_t)i * ld + col] = 0.0;
+    }
+    // ---- residual column and padding
+    for (int i = tid; i < Np; i += blockDim.x) {
+        double v = 0.0;
+        const double *rc = qpe + (int64_t)kVJac * Nq + (int64_t)(4 * r) * Nq;
+        const int i1 = i % p1, i2 = (i / p1) % p1, i3 = i / (p1 * p1);
+        for (int g = 0; g < Nq; ++g) {
+            const int g1 = g % nq, g2 = (g / nq) % nq, g3 = g / (nq * nq);
+            const double l0 = sL[i1][g1], l1 = sL[i2][g2], l2 = sL[i3][g3];
+            v += rc[g] * l0 * l1 * l2 + rc[Nq + g] * sD[i1][g1] * l1 * l2 + rc[2 * Nq + g] * l0 * sD[i2][g2] * l2 +
+                 rc[3 * Nq + g] * l0 * l1 * sD[i3][g3];
         }
+        for (int lf = 0; lf < 6; ++lf) {
+            int a0, a1;
+            if (!face_idx(i1, i2, i3, lf, a0, a1)) continue;
+            const int Nqf = sNqf[lf], nqf1 = sPf[lf] + 2;
+            const double *fb = qpe + sFbase[lf];
+            const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
+            for (int s = 0; s < Nqf; ++s) {
+                const double ph = sLf[lf][a0 * nqf1 + s % nqf1] * sLf[lf][a1 * nqf1 + s / nqf1];
+                if (qrow) v -= fgl[jdir * Nqf + s] * fb[(135 + c) * Nqf + s] * ph;
+                else v += P.dt * fb[(125 + c) * Nqf + s] * ph;
+            }
+        }
+        Er[(int64_t)i * ld + n + f] = v;
+        for (int64_t col = n + f + 1; col < ld; ++col) Er[(int64_t)i * ld + col] = 0.0;
     }
 }
 
@@ -660,15 +647,8 @@ int launch_element_system(const hdg_ctx *ctx, int e0, int ne, const double *Q, c
     const Phys P = ctx->phys;
     hipLaunchKernelGGL(k_qp_volume, dim3(ne), dim3(256), 0, s, dm, P, e0, Q, U, Un, nu, qp);
     hipLaunchKernelGGL(k_qp_face, dim3(6, ne), dim3(64), 0, s, dm, P, e0, Q, U, Uhat, nu, Ub, qp);
-    int maxp = 1;
-    for (int e = e0; e < e0 + ne; ++e) maxp = std::max(maxp, ctx->elem_p[e]);
     const double *qpc = qp;
-    switch (maxp) {
-        case 1: hipLaunchKernelGGL(k_assemble_interior<1>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
-        case 2: hipLaunchKernelGGL(k_assemble_interior<2>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
-        case 3: hipLaunchKernelGGL(k_assemble_interior<4>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
-        default: hipLaunchKernelGGL(k_assemble_interior<8>, dim3(8, ne), dim3(256), 0, s, dm, P, e0, qpc, E); break;
-    }
+    hipLaunchKernelGGL(k_assemble_field_rows, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
     hipLaunchKernelGGL(k_assemble_trace_rows, dim3(6, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
     return (int)hipGetLastError();
 }
