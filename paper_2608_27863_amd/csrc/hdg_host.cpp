@@ -298,7 +298,7 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
         ctx->qp_off[e + 1] = ctx->qp_off[e] + (int64_t)(hdg::kVJac + hdg::kVRes) * Nq + (int64_t)hdg::kFPer * nqf_tot;
         ctx->vgeo_off[e + 1] = ctx->vgeo_off[e] + 10 * Nq;
         const int fe = hdg::asm_pad(f);  // Schwarz system size
-        ctx->asmsys_off[e + 1] = ctx->asmsys_off[e] + (int64_t)(2 * fe) * hdg::e_ld(fe, fe);
+        ctx->asmsys_off[e + 1] = ctx->asmsys_off[e] + (int64_t)fe * hdg::e_ld(fe, fe);
         ctx->tloc_off[e + 1] = ctx->tloc_off[e] + f;
         ctx->m32_off[e + 1] = ctx->m32_off[e] + (int64_t)n * hdg::e_ld(n, f);
         ctx->x_off[e + 1] = ctx->x_off[e] + (int64_t)n * hdg::x_ld(f);

@@ -50,7 +50,7 @@ struct DevMesh {
     const int64_t *SK_off;     // [n_elem+1]
     const int64_t *asm_off;    // [n_elem+1]
     const int64_t *qp_off;     // [n_elem+1]
-    const int64_t *asmsys_off; // [n_elem+1] Schwarz inversion systems (2m x ld entries, m = asm_pad(f))
+    const int64_t *asmsys_off; // [n_elem+1] Schwarz inversion systems [S_r | I] (m x ld entries, m = asm_pad(f))
     const int64_t *tloc_off;   // [n_elem+1] prefix sums of f_e (element-local trace vectors)
     const int64_t *m32_off;    // [n_elem+1] FP32 interior systems [A | B R_qu] (n x e_ld floats)
     const int64_t *x_off;      // [n_elem+1] X = A^{-1}[B | R_qu] (n x x_ld doubles)
@@ -119,6 +119,7 @@ int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *
 int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info,
                      void *work, hipStream_t s);
 size_t asm_setup_work_bytes(const hdg_ctx *ctx, int prec);
+size_t schwarz_ws_bytes(const hdg_ctx *ctx, int prec);
 int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
                      void *work, hipStream_t s);
 size_t asm_apply_work_bytes(const hdg_ctx *ctx);

@@ -96,8 +96,8 @@ struct ElemDims {
     int64_t ld;
 };
 // Systems factored here: mode 0 = element systems (n = 20 N_p, f = f_e, all
-// n + f rows); mode 1 = Schwarz inversion systems [[S_r, I], [I, 0]] (n = f = f_r
-// rounded up to a multiple of 4); mode 2 = FP32 interior rows [A | B R_qu] (n rows).
+// n + f rows); mode 1 = Schwarz inversion systems [S_r | I] (n = f = f_r rounded up
+// to a multiple of 4, n rows); mode 2 = FP32 interior rows [A | B R_qu] (n rows).
 struct SysDesc {
     int mode;
     const int64_t *off;  // [n_elem+1] offsets (elements) of the systems
@@ -113,7 +113,7 @@ __device__ inline ElemDims elem_dims(const DevMesh &dm, const SysDesc &sd, int e
         d.n = asm_pad(dm.toff[7 * e + 6]);
         d.f = d.n;
     }
-    d.mrows = (sd.mode == 2) ? d.n : d.n + d.f;
+    d.mrows = (sd.mode == 0) ? d.n + d.f : d.n;
     d.ncols = d.n + d.f + 1;
     d.ld = e_ld(d.n, d.f);
     return d;
@@ -877,7 +877,7 @@ __global__ void k_zero_int(int *p, int n) {
 // X_b = U_b^{-1} Y_b, Y_a -= U_ab X_b, X_a = U_a^{-1} Y_a (U_a, U_b: the diagonal
 // 64-blocks, U_ab the block above U_b), in place.  One workgroup per
 // (64-column tile, element).
-template <typename T>
+template <int TAG, typename T>
 __global__ void __launch_bounds__(256) k_bsolve(DevMesh dm, SysDesc sd, int e0, int k0, T *__restrict__ Ebase,
                                                 WS<T> ws) {
     typedef typename MF<T>::acc_t acc_t;
@@ -1225,19 +1225,79 @@ size_t bordered_lu_work(const hdg_ctx *ctx, int ne) {
     return sizeof(double) * (size_t)ne * kWsDbl + sizeof(int) * (size_t)ne * kWsInt;
 }
 
-// Schwarz blocks: systems [[S_r, I], [I, 0]] in `sys` (offsets asmsys_off, FP64 or
-// FP32 entries), eliminated over the first m_r columns; the trailing block is -S_r^{-1}.
+template <typename T> static WS<T> block_ws(WS<T> ws, int k0) {
+    ws.d += (int64_t)(k0 / kNBO) * kWsDbl;
+    ws.i += (int64_t)(k0 / kNBO) * kWsInt;
+    return ws;
+}
+
+// Back substitution U X = Y on the right-hand columns n .. ncols of factored
+// systems (the per-block records in ws kept by run_lu with persist), in place.
+template <typename T, int TAG>
+static void run_back_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, WS<T> ws, int maxn,
+                           int rhs_cols, hipStream_t s) {
+    const DevMesh &dm = ctx->dm;
+    const int tn = (rhs_cols + kTN - 1) / kTN;
+    for (int k0 = (maxn - 1) / kNBO * kNBO; k0 >= 0; k0 -= kNBO) {
+        hipLaunchKernelGGL((k_bsolve<TAG, T>), dim3((rhs_cols + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, E,
+                           block_ws(ws, k0));
+        if (k0 > 0) {
+            const int tm = (k0 + kTM - 1) / kTM;
+            hipLaunchKernelGGL((k_update<T, TAG, kRangeBwd>), dim3((ne * tm * tn + 7) / 8 * 8), dim3(256), 0, s, dm, sd,
+                               e0, ne, k0, kNBO, 0, tm, tn, E);
+        }
+    }
+}
+
+// Forward substitution L Y = P R of new right-hand columns, replaying the
+// recorded permutations block by block.
+template <typename T, int TAG>
+static void run_forward_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, WS<T> ws, int maxn,
+                              int rhs_cols, hipStream_t s) {
+    const DevMesh &dm = ctx->dm;
+    const int tn = (rhs_cols + kTN - 1) / kTN;
+    for (int k0 = 0; k0 < maxn; k0 += kNBO) {
+        hipLaunchKernelGGL((k_rowperm<2, TAG, T>), dim3((rhs_cols + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm, sd, e0,
+                           k0, 0, 1, E, block_ws(ws, k0));
+        const int rows = maxn - k0 - kNBO;
+        if (rows > 0) {
+            const int tm = (rows + kTM - 1) / kTM;
+            hipLaunchKernelGGL((k_update<T, TAG, kRangeFwd>), dim3((ne * tm * tn + 7) / 8 * 8), dim3(256), 0, s, dm, sd,
+                               e0, ne, k0, kNBO, 0, tm, tn, E);
+        }
+    }
+}
+
+// Schwarz blocks: systems [S_r | I] in `sys` (offsets asmsys_off, FP64 or FP32
+// entries): LU with partial pivoting, then back substitution on the identity
+// columns, which then hold S_r^{-1}.
+static int schwarz_nblk(const hdg_ctx *ctx) { return std::max(1, (asm_pad(ctx->max_f) + kNBO - 1) / kNBO); }
+
+size_t schwarz_ws_bytes(const hdg_ctx *ctx, int prec) {
+    const size_t es = (prec == HDG_FP64) ? sizeof(double) : sizeof(float);
+    const size_t per = (size_t)schwarz_nblk(ctx) * ((size_t)kWsDbl * es + (size_t)kWsInt * sizeof(int));
+    return per * (size_t)ctx->n_elem + 256;
+}
+
 int run_asm_inversion(const hdg_ctx *ctx, int prec, void *sys, int *info, void *iwork, hipStream_t s) {
     const SysDesc sd{1, ctx->dm.asmsys_off};
-    const int maxf = asm_pad(ctx->max_f);
+    const int m = asm_pad(ctx->max_f);
     const int ne = ctx->n_elem;
-    int *wi = (int *)((char *)iwork + sizeof(double) * (size_t)ne * kWsDbl);
+    const int nblk = schwarz_nblk(ctx);
+    const size_t es = (prec == HDG_FP64) ? sizeof(double) : sizeof(float);
+    int *wi = (int *)((char *)iwork + ((es * (size_t)ne * nblk * kWsDbl + 255) / 256 * 256));
     if (prec == HDG_FP64) {
-        WS<double> ws{(double *)iwork, wi, kWsDbl, kWsInt};
-        return run_lu<double, 1>(ctx, sd, 0, ne, (double *)sys, info, ws, false, maxf, 2 * maxf, 2 * maxf + 1, maxf, s);
+        WS<double> ws{(double *)iwork, wi, (int64_t)nblk * kWsDbl, (int64_t)nblk * kWsInt};
+        int err = run_lu<double, 1>(ctx, sd, 0, ne, (double *)sys, info, ws, true, m, m, 2 * m + 1, 0, s);
+        if (err) return err;
+        run_back_solve<double, 1>(ctx, sd, 0, ne, (double *)sys, ws, m, m + 1, s);
+    } else {
+        WS<float> ws{(float *)iwork, wi, (int64_t)nblk * kWsDbl, (int64_t)nblk * kWsInt};
+        int err = run_lu<float, 3>(ctx, sd, 0, ne, (float *)sys, info, ws, true, m, m, 2 * m + 1, 0, s);
+        if (err) return err;
+        run_back_solve<float, 3>(ctx, sd, 0, ne, (float *)sys, ws, m, m + 1, s);
     }
-    WS<float> ws{(float *)iwork, wi, kWsDbl, kWsInt};
-    return run_lu<float, 3>(ctx, sd, 0, ne, (float *)sys, info, ws, false, maxf, 2 * maxf, 2 * maxf + 1, maxf, s);
+    return (int)hipGetLastError();
 }
 
 // ---------------------------------------------------------------- mixed path
@@ -1275,38 +1335,9 @@ int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double
                  (int64_t)L.nblk * kWsInt};
     const SysDesc sd{2, dm.m32_off};
     const int rhs_cols = maxf + 1;
-    const dim3 rhs_grid((rhs_cols + 63) / 64, ne);
-    auto block_ws = [&](int k0) {
-        WS<float> w = ws;
-        w.d += (int64_t)(k0 / kNBO) * kWsDbl;
-        w.i += (int64_t)(k0 / kNBO) * kWsInt;
-        return w;
-    };
+    auto back_solve = [&]() { run_back_solve<float, 2>(ctx, sd, e0, ne, M, ws, maxn, rhs_cols, s); };
+    auto forward_solve = [&]() { run_forward_solve<float, 2>(ctx, sd, e0, ne, M, ws, maxn, rhs_cols, s); };
     const int tn = (rhs_cols + kTN - 1) / kTN;
-    auto rhs_update = [&](bool fwd, int k0, int rows) {
-        if (rows <= 0) return;
-        const int tm = (rows + kTM - 1) / kTM;
-        const dim3 grid((ne * tm * tn + 7) / 8 * 8);
-        if (fwd)
-            hipLaunchKernelGGL((k_update<float, 2, kRangeFwd>), grid, dim3(256), 0, s, dm, sd, e0, ne, k0, kNBO, 0, tm,
-                               tn, M);
-        else
-            hipLaunchKernelGGL((k_update<float, 2, kRangeBwd>), grid, dim3(256), 0, s, dm, sd, e0, ne, k0, kNBO, 0, tm,
-                               tn, M);
-    };
-    auto back_solve = [&]() {
-        for (int k0 = (maxn - 1) / kNBO * kNBO; k0 >= 0; k0 -= kNBO) {
-            hipLaunchKernelGGL((k_bsolve<float>), rhs_grid, dim3(256), 0, s, dm, sd, e0, k0, M, block_ws(k0));
-            rhs_update(false, k0, k0);
-        }
-    };
-    auto forward_solve = [&]() {
-        for (int k0 = 0; k0 < maxn; k0 += kNBO) {
-            hipLaunchKernelGGL((k_rowperm<2, 2, float>), dim3((rhs_cols + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm,
-                               sd, e0, k0, 0, 1, M, block_ws(k0));
-            rhs_update(true, k0, maxn - k0 - kNBO);
-        }
-    };
     const dim3 elem_grid(64, ne);
     hipLaunchKernelGGL(k_to32, elem_grid, dim3(256), 0, s, dm, e0, (const double *)E, M);
     // FP32 LU of A with the forward substitution of [B | R_qu] carried along, then X_0

@@ -122,33 +122,29 @@ __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__r
     const int f = to[6], m = asm_pad(f);
     const int64_t ld = e_ld(m, m);
     T *base = sys + dm.asmsys_off[e];
-    const int64_t total = (int64_t)2 * m * ld;
+    const int64_t total = (int64_t)m * ld;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(t / ld), c = (int)(t % ld);
         double v = 0.0;
-        if (r < m) {
-            if (c < m) {
-                if (r < f && c < f) {
-                    int a = 0, b = 0;
-                    while (r >= to[a + 1]) ++a;
-                    while (c >= to[b + 1]) ++b;
-                    const int k = dm.asm_blk[36 * e + 6 * a + b];
-                    const int bF = to[a + 1] - to[a];
-                    v = S[dm.bsr_val_off[k] + (r - to[a]) + (int64_t)(c - to[b]) * bF];
-                } else {
-                    v = (r == c) ? 1.0 : 0.0;
-                }
-            } else if (c < 2 * m) {
-                v = (c - m == r) ? 1.0 : 0.0;
+        if (c < m) {
+            if (r < f && c < f) {
+                int a = 0, b = 0;
+                while (r >= to[a + 1]) ++a;
+                while (c >= to[b + 1]) ++b;
+                const int k = dm.asm_blk[36 * e + 6 * a + b];
+                const int bF = to[a + 1] - to[a];
+                v = S[dm.bsr_val_off[k] + (r - to[a]) + (int64_t)(c - to[b]) * bF];
+            } else {
+                v = (r == c) ? 1.0 : 0.0;
             }
-        } else if (c < m) {
-            v = (c == r - m) ? 1.0 : 0.0;
+        } else if (c < 2 * m) {
+            v = (c - m == r) ? 1.0 : 0.0;
         }
         base[t] = (T)v;
     }
 }
 
-// Sinv (column-major f x f) = -(trailing block)
+// Sinv (column-major f x f) = the identity columns after the solve
 template <typename T>
 __global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const T *__restrict__ sys, T *__restrict__ Sinv) {
     const int e = blockIdx.z;
@@ -162,7 +158,7 @@ __global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const T *__rest
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = i0 + r, j = j0 + tx;
-        tile[r][tx] = (i < f && j < f) ? -base[(int64_t)(m + i) * ld + m + j] : T(0);
+        tile[r][tx] = (i < f && j < f) ? base[(int64_t)i * ld + m + j] : T(0);
     }
     __syncthreads();
     for (int c = ty; c < 32; c += 8) {
@@ -419,8 +415,7 @@ int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *
 size_t asm_setup_work_bytes(const hdg_ctx *ctx, int prec) {
     const size_t es = (prec == HDG_FP64) ? sizeof(double) : sizeof(float);
     size_t sys = es * (size_t)ctx->asmsys_off[ctx->n_elem];
-    size_t iw = bordered_lu_work(ctx, ctx->n_elem);
-    return (sys + 255) / 256 * 256 + (iw + 255) / 256 * 256;
+    return (sys + 255) / 256 * 256 + (schwarz_ws_bytes(ctx, prec) + 255) / 256 * 256;
 }
 
 int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info, void *work,
