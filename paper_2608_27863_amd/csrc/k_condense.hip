@@ -69,6 +69,7 @@ template <> struct MF<float> {
 constexpr int kNB = 64;       // panel width
 constexpr int kNBO = 128;     // pivot columns per trailing update
 constexpr int kW = 8;         // register sub-panel width
+constexpr int kHalf = 32;     // the panel is factored as two halves (sub-panels update only within a half)
 constexpr int kPT = 512;      // panel kernel threads
 constexpr int kRPC = 32;      // columns per k_rowperm workgroup
 static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptions");
@@ -168,7 +169,10 @@ __device__ void block_net_perm(int base, int w, const int *piv, int *top_src, in
 // ------------------------------------------------------------------ panel
 // Factor the panel columns [k0, k0+nb) over the pivot rows [k0, n) (the trace
 // rows n.. get their multipliers from k_crows).  Rows are distributed over the
-// threads (row cb + tid + kPT i), kW columns at a time held in registers.
+// threads (row cb + tid + kPT i), kW columns at a time held in registers.  The
+// panel is two halves: sub-panels update the columns of their own half only, and
+// the second half receives the whole first half's update in one pass (which
+// reads and writes the panel's right part far fewer times).
 template <int R, int TAG, typename T>
 __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase,
                                                T *__restrict__ Ebase, WS<T> ws, int *__restrict__ info) {
@@ -338,9 +342,12 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
             }
             __syncthreads();
         }
-        if (nright > 0) {
+        // sub-panels of the first half update only the first half's columns; the
+        // second half receives the first half's update in one pass below
+        const int nrloc = (j0 + w <= kHalf && nb > kHalf) ? kHalf - j0 - w : nright;
+        if (nrloc > 0) {
             // U of the sub-panel rows in the right columns: unit lower solve
-            for (int cidx = tid; cidx < nright; cidx += kPT) {
+            for (int cidx = tid; cidx < nrloc; cidx += kPT) {
                 const int col = cb + w + cidx;
                 T x[kW];
 #pragma unroll
@@ -362,17 +369,71 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
                 const int r = cb + tid + kPT * i;
                 if (r < cb + w || r >= n) continue;
                 T *row = E + (int64_t)r * ld + cb + w;
-                for (int c8 = 0; c8 < nright; c8 += 8) {
+                for (int c8 = 0; c8 < nrloc; c8 += 8) {
                     T v[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = (c8 + q < nright) ? row[c8 + q] : T(0);
+                    for (int q = 0; q < 8; ++q) v[q] = (c8 + q < nrloc) ? row[c8 + q] : T(0);
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
 #pragma unroll
                         for (int q = 0; q < 8; ++q) v[q] -= a[i][jj] * s_U[jj][(c8 + q) & (kNB - 1)];
 #pragma unroll
                     for (int q = 0; q < 8; ++q)
-                        if (c8 + q < nright) row[c8 + q] = v[q];
+                        if (c8 + q < nrloc) row[c8 + q] = v[q];
+                }
+            }
+            __syncthreads();
+        }
+        if (nb > kHalf && j0 + w == kHalf) {
+            // second half: U12 = L11^{-1} A12 on the top kHalf rows (one thread per
+            // column), then A22 -= L21 U12 for every pivot row below
+            const int nb2 = nb - kHalf;
+            for (int t = tid; t < kHalf * kHalf; t += kPT) {
+                const int r = t / kHalf, c = t % kHalf;
+                s_T[r][c] = E[(int64_t)(k0 + r) * ld + k0 + c];
+                s_I[r][c] = (c < nb2) ? E[(int64_t)(k0 + r) * ld + k0 + kHalf + c] : T(0);
+            }
+            __syncthreads();
+            if (tid < nb2) {
+                for (int r = 1; r < kHalf; ++r) {
+                    T x = s_I[r][tid];
+                    for (int rr = 0; rr < r; ++rr) x -= s_T[r][rr] * s_I[rr][tid];
+                    s_I[r][tid] = x;
+                }
+            }
+            __syncthreads();
+            for (int t = tid; t < kHalf * nb2; t += kPT) {
+                const int r = t / nb2, c = t % nb2;
+                E[(int64_t)(k0 + r) * ld + k0 + kHalf + c] = s_I[r][c];
+            }
+            // A22 -= L21 U12, one pivot row per thread, 8 columns x 8 inner indices
+            // at a time (short loops keep the live registers few)
+#pragma unroll 1
+            for (int r = k0 + kHalf + tid; r < n; r += kPT) {
+                const T *src = E + (int64_t)r * ld + k0;
+                T *row = E + (int64_t)r * ld + k0 + kHalf;
+#pragma unroll 1
+                for (int c8 = 0; c8 < nb2; c8 += 8) {
+                    T v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) v[q] = (c8 + q < nb2) ? row[c8 + q] : T(0);
+#pragma unroll 1
+                    for (int kb = 0; kb < kHalf; kb += 8) {
+                        T l8[8];
+#pragma unroll
+                        for (int c = 0; c < 8; c += 2) {
+                            const v2 lv = *(const v2 *)(src + kb + c);
+                            l8[c] = lv.x;
+                            l8[c + 1] = lv.y;
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) v[q] -= l8[kk] * s_I[kb + kk][(c8 + q) & (kHalf - 1)];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (c8 + q < nb2) row[c8 + q] = v[q];
                 }
             }
             __syncthreads();
