@@ -22,9 +22,12 @@
 //                sub-panels held in registers), records its pivots, the net row
 //                permutation, L11^{-1} and U11^{-1}
 //   k_crows      multipliers of the trace rows, L_C = C_panel U11^{-1}
-//   k_rowperm    applies a recorded permutation to a range of columns and forms
-//                U12 = L11^{-1} P A12 with matrix cores (for the 128-row block:
-//                U_a = La^{-1} X_a, X_b -= L_ba U_a, U_b = Lb^{-1} X_b)
+//   k_rowperm    within the block: applies panel a's permutation to panel b's
+//                columns and forms its U rows; applies panel b's permutation
+//                to panel a's L
+//   k_linv128    the (2,1) block of the 128-row unit lower triangle's inverse
+//   k_blocku     trailing columns: the block's net row permutation and
+//                U12 = L11^{-1} P A12 as one triangular product on matrix cores
 //   k_update     A22 -= L21 U12 on matrix cores (16x16x4): first over the second
 //                panel's columns (K = 64), then over every trailing column with
 //                K = 128, which halves the trailing-matrix traffic of a 64-wide
@@ -72,16 +75,19 @@ constexpr int kW = 8;         // register sub-panel width
 constexpr int kHalf = 32;     // the panel is factored as two halves (sub-panels update only within a half)
 constexpr int kPT = 512;      // panel kernel threads
 constexpr int kRPC = 32;      // columns per k_rowperm workgroup
+constexpr int kBC = 32;       // columns per k_blocku workgroup
 static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptions");
 // A recorded permutation of w swaps (row base+jj <-> piv[jj]): [0] = number of
 // displaced rows, [1 .. W] source row of each top row, then (dst, src) pairs.
 constexpr int kPerm64 = 1 + kNB + 2 * kNB;
 constexpr int kPerm128 = 1 + kNBO + 2 * kNBO;
-// Workspace of one element and one 128-column block: values [4][64*64] (L^{-1}
-// of panels 0, 1, then U^{-1} of panels 0, 1), then ints: piv[128] | perm of
-// panel 0 | perm of panel 1 | perm of the 128 block.  The FP64 path reuses one
-// block's worth per element; the mixed path keeps every block (its solves replay them).
-constexpr int kWsDbl = 4 * kNB * kNB;
+// Workspace of one element and one 128-column block: values [5][64*64] (L^{-1}
+// of panels 0, 1, then U^{-1} of panels 0, 1, then the block Lc of the 128-row
+// inverse, below), then ints: piv[128] | perm of panel 0 | perm of panel 1 |
+// perm of the 128 block.  The FP64 path reuses one block's worth per element;
+// the mixed path keeps every block (its solves replay them).
+constexpr int kWsDbl = 5 * kNB * kNB;
+constexpr int kWsLc = 4 * kNB * kNB;
 constexpr int kWsPiv = 0, kWsPerm0 = kNBO, kWsPerm1 = kWsPerm0 + kPerm64, kWsPerm128 = kWsPerm1 + kPerm64;
 constexpr int kWsInt = kWsPerm128 + kPerm128;
 
@@ -617,13 +623,10 @@ __global__ void __launch_bounds__(256) k_crows(DevMesh dm, SysDesc sd, int e0, i
 // MODE 0: rows base..base+63 <- permuted (panel 0), U = L^{-1} X, on
 //         columns [k0 + K_e, k0 + min(CW, n_e - k0))  (CW = 0: to the end)
 // MODE 1: permutation of panel 1 only, on the columns of panel 0 (its L)
-// MODE 2: 128-row block: X = P A12 (net permutation of both panels),
-//         U_a = La^{-1} X_a, X_b -= L_ba U_a, U_b = Lb^{-1} X_b, on the trailing
-//         columns (rhs = 1: on the right-hand columns n.. only, which replays the
-//         block's forward substitution on a new right-hand side)
-// One workgroup per (32-column tile, element).
+// One workgroup per (32-column tile, element).  (The 128-row block of the
+// trailing columns is k_blocku's.)
 template <int MODE, int TAG, typename T>
-__global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0, int k0, int CW, int rhs,
+__global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0, int k0, int CW,
                                                  T *__restrict__ Ebase, WS<T> ws) {
     typedef typename MF<T>::acc_t acc_t;
     const int e = e0 + blockIdx.y;
@@ -636,27 +639,22 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
         c_begin = k0 + K;
         c_end = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
         base = k0; nrows = K; permoff = kWsPerm0;
-    } else if (MODE == 1) {
+    } else {
         if (rem <= kNB) return;
         c_begin = k0;
         c_end = k0 + kNB;
         base = k0 + kNB; nrows = min(kNB, rem - kNB); permoff = kWsPerm1;
-    } else {
-        const int nbo = min(kNBO, rem);
-        c_begin = rhs ? dd.n : k0 + nbo;
-        c_end = dd.ncols;
-        base = k0; nrows = nbo; permoff = (nbo > kNB) ? kWsPerm128 : kWsPerm0;
     }
     const int c0 = c_begin + blockIdx.x * kRPC;
     if (c0 >= c_end) return;  // uniform per block
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ T sX[kNBO][kRPC + 1];
+    __shared__ T sX[kNB][kRPC + 1];
     __shared__ T sM[kNB][kNB + 1];
-    __shared__ int sperm[kPerm128];
+    __shared__ int sperm[kPerm64];
     const int *wi = ws.i + (int64_t)blockIdx.y * ws.is;
-    const int W = (permoff == kWsPerm128) ? kNBO : kNB;
+    constexpr int W = kNB;
     const int permlen = 1 + W + 2 * W;
     for (int t = tid; t < permlen; t += 256) sperm[t] = wi[permoff + t];
     __syncthreads();
@@ -665,7 +663,7 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
         const int r = t / kRPC, c = t % kRPC;
         sX[r][c] = (c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : T(0);
     }
-    for (int t = tid; t < (kNBO - nrows) * kRPC; t += 256) sX[nrows + t / kRPC][t % kRPC] = T(0);
+    for (int t = tid; t < (kNB - nrows) * kRPC; t += 256) sX[nrows + t / kRPC][t % kRPC] = T(0);
     // a top row's source may be a displaced row: its old content must be read
     // before the displaced copies overwrite it
     __syncthreads();
@@ -680,7 +678,7 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
         }
     }
     if (MODE == 1) __syncthreads();
-    if (MODE != 1) {
+    if (MODE == 0) {
         const T *la = ws.d + (int64_t)blockIdx.y * ws.ds;
         acc_t acc[kRPC / 16];
         // U_a = La^{-1} X_a
@@ -692,38 +690,160 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
         for (int j = 0; j < kRPC / 16; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) sX[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
-        if (nrows > kNB) {
-            // X_b -= L_ba U_a   (L_ba: rows base+64.., columns base.. of E, already permuted)
-            __syncthreads();
-            for (int t = tid; t < kNB * kNB; t += 256) {
-                const int r = t >> 6, c = t & 63;
-                sM[r][c] = (kNB + r < nrows) ? E[(int64_t)(base + kNB + r) * ld + base + c] : T(0);
-            }
-            __syncthreads();
-            mfma_64xc<T, kRPC>(sM, sX, acc, lane, wave);
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kRPC / 16; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] -= acc[j][q];
-            // U_b = Lb^{-1} X_b
-            __syncthreads();
-            for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = la[kNB * kNB + t];
-            __syncthreads();
-            mfma_64xc<T, kRPC>(sM, (const T (*)[kRPC + 1])(&sX[kNB][0]), acc, lane, wave);
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kRPC / 16; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
-        }
         __syncthreads();
     }
     for (int t = tid; t < nrows * kRPC; t += 256) {
         const int r = t / kRPC, c = t % kRPC;
         if (c0 + c < c_end) E[(int64_t)(base + r) * ld + c0 + c] = sX[r][c];
+    }
+}
+
+// ------------------------------------------- 128-row block forward solve
+// The unit lower triangle of a 128-column block (panels a and b) has the inverse
+// [[La^{-1}, 0], [Lc, Lb^{-1}]], Lc = -Lb^{-1} L_ba La^{-1}.  k_linv128 forms Lc
+// once per element, after panel b's swaps have reached L_ba (rows base+64..,
+// columns base..base+63 of E), and records it in the block's workspace.
+template <int TAG, typename T>
+__global__ void __launch_bounds__(256) k_linv128(DevMesh dm, SysDesc sd, int e0, int k0,
+                                                 const T *__restrict__ Ebase, WS<T> ws) {
+    typedef typename MF<T>::acc_t acc_t;
+    const int e = e0 + blockIdx.x;
+    const ElemDims dd = elem_dims(dm, sd, e);
+    if (k0 >= dd.n || dd.n - k0 <= kNB) return;
+    const int nb1 = min(kNB, dd.n - k0 - kNB);
+    const T *E = Ebase + (sd.off[e] - sd.off[e0]);
+    const int64_t ld = dd.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ T sL[kNB][kNB + 1], sR[kNB][kNB + 1];
+    T *wd = ws.d + (int64_t)blockIdx.x * ws.ds;
+    for (int t = tid; t < kNB * kNB; t += 256) {
+        const int r = t >> 6, c = t & 63;
+        sL[r][c] = (r < nb1) ? E[(int64_t)(k0 + kNB + r) * ld + k0 + c] : T(0);
+        sR[r][c] = wd[t];
+    }
+    __syncthreads();
+    acc_t acc[4];
+    mfma_64x64<T>(sL, sR, acc, lane, wave);  // L_ba La^{-1}
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sR[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
+    for (int t = tid; t < kNB * kNB; t += 256) sL[t >> 6][t & 63] = wd[kNB * kNB + t];
+    __syncthreads();
+    mfma_64x64<T>(sL, sR, acc, lane, wave);  // Lb^{-1} L_ba La^{-1}
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            wd[kWsLc + (16 * wave + MF<T>::rowof(lane, q)) * kNB + 16 * j + (lane & 15)] = -acc[j][q];
+}
+
+// One 32-column tile of the columns right of a block of nrows = min(128, n - k0)
+// pivot columns: X = P A12 (the block's net row permutation: permuted top rows
+// gathered into LDS, displaced rows moved), then U12 = L11^{-1} X in a single
+// product with the recorded inverse.  The zero blocks of the triangle are
+// skipped; wave w takes the 16-row blocks w and 7 - w, whose inner lengths
+// 16 (w + 1) and 16 (8 - w) give every wave the same work.  L11^{-1} is read
+// from the cache in matrix-core operand order, X from LDS.  rhs = 1: only the
+// right-hand columns n.. (replays the block's forward substitution).  One
+// workgroup per (tile, element); an element's tiles share an XCD.
+template <int TAG, typename T>
+__global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int rhs, int tiles,
+                                                T *__restrict__ Ebase, WS<T> ws) {
+    typedef typename MF<T>::acc_t acc_t;
+    const int total = ne * tiles;
+    const int per_xcd = (total + 7) / 8;
+    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= total) return;
+    const int el = w / tiles;
+    const int e = e0 + el;
+    const ElemDims dd = elem_dims(dm, sd, e);
+    if (k0 >= dd.n) return;
+    const int nrows = min(kNBO, dd.n - k0);
+    const int c_end = dd.ncols;
+    const int c0 = (rhs ? dd.n : k0 + nrows) + (w % tiles) * kBC;
+    if (c0 >= c_end) return;  // uniform per block
+    T *E = Ebase + (sd.off[e] - sd.off[e0]);
+    const int64_t ld = dd.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ T sX[kNBO][kBC + 1];
+    __shared__ int sperm[kPerm128];
+    const int *wi = ws.i + (int64_t)el * ws.is;
+    const T *wd = ws.d + (int64_t)el * ws.ds;
+    const bool two = nrows > kNB;
+    const int W = two ? kNBO : kNB;
+    const int permoff = two ? kWsPerm128 : kWsPerm0;
+    for (int t = tid; t < 1 + 3 * W; t += 256) sperm[t] = wi[permoff + t];
+    __syncthreads();
+    // gather the permuted top rows (rows >= nrows are zero)
+#pragma unroll
+    for (int q = 0; q < kNBO * kBC / 256; ++q) {
+        const int t = tid + 256 * q;
+        const int r = t / kBC, c = t % kBC;
+        sX[r][c] = (r < nrows && c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : T(0);
+    }
+    // a top row's source may be a displaced row: its old content must be read
+    // before the displaced copies overwrite it
+    __syncthreads();
+    // displaced rows take original top rows, which are rewritten only after the
+    // next barrier
+    const int nd = sperm[0];
+#pragma unroll 4
+    for (int t = tid; t < nd * kBC; t += 256) {
+        const int d = t / kBC, c = t % kBC;
+        if (c0 + c < c_end) {
+            const int dst = sperm[1 + W + 2 * d], src = sperm[1 + W + 2 * d + 1];
+            E[(int64_t)dst * ld + c0 + c] = E[(int64_t)src * ld + c0 + c];
+        }
+    }
+    // U12 = L11^{-1} X
+    const int kq = lane >> 4, cl = lane & 15;
+    acc_t acc[2][kBC / 16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int rb = h == 0 ? wave : 7 - wave;
+#pragma unroll
+        for (int j = 0; j < kBC / 16; ++j) acc[h][j] = (acc_t){T(0), T(0), T(0), T(0)};
+        if (16 * rb >= nrows) continue;  // uniform per wave
+        const int r = 16 * rb + cl;
+        if (rb < 4) {
+            const T *arow = wd + r * kNB + kq;  // La^{-1}
+#pragma unroll 4
+            for (int kk = 0; kk < 16 * (rb + 1); kk += 4) {
+                const T a = arow[kk];
+#pragma unroll
+                for (int j = 0; j < kBC / 16; ++j) acc[h][j] = MF<T>::mfma(a, sX[kk + kq][16 * j + cl], acc[h][j]);
+            }
+        } else {
+            const T *crow = wd + kWsLc + (r - kNB) * kNB + kq;  // Lc
+#pragma unroll 4
+            for (int kk = 0; kk < kNB; kk += 4) {
+                const T a = crow[kk];
+#pragma unroll
+                for (int j = 0; j < kBC / 16; ++j) acc[h][j] = MF<T>::mfma(a, sX[kk + kq][16 * j + cl], acc[h][j]);
+            }
+            const T *brow = wd + kNB * kNB + (r - kNB) * kNB + kq;  // Lb^{-1}
+#pragma unroll 4
+            for (int kk = 0; kk < 16 * (rb - 3); kk += 4) {
+                const T a = brow[kk];
+#pragma unroll
+                for (int j = 0; j < kBC / 16; ++j)
+                    acc[h][j] = MF<T>::mfma(a, sX[kNB + kk + kq][16 * j + cl], acc[h][j]);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int rb = h == 0 ? wave : 7 - wave;
+#pragma unroll
+        for (int j = 0; j < kBC / 16; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 16 * rb + MF<T>::rowof(lane, q), c = c0 + 16 * j + cl;
+                if (r < nrows && c < c_end) E[(int64_t)(k0 + r) * ld + c] = acc[h][j][q];
+            }
     }
 }
 
@@ -1241,19 +1361,18 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
         panel(k0, 0);
         if (maxn - k0 > kNB) {
             // rest of the 128-column block, then its second panel
-            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, kNBO, 0, E, wb);
+            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, kNBO, E, wb);
             update(kNB, kNBO, maxm - k0, kNB);
             panel(k0 + kNB, 1);
-            hipLaunchKernelGGL((k_rowperm<1, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0, E, wb);
-            // trailing columns: 128-row permutation + block solve, K = 128 update
-            hipLaunchKernelGGL((k_rowperm<2, TAG, T>), dim3((ncol + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
-                               E, wb);
-            update(kNBO, 0, maxm - k0, ncol);
-        } else {
-            hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3((ncol + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, 0,
-                               E, wb);
-            update(kNB, 0, maxm - k0, ncol);
+            hipLaunchKernelGGL((k_rowperm<1, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, E, wb);
+            hipLaunchKernelGGL((k_linv128<TAG, T>), dim3(ne), dim3(256), 0, s, dm, sd, e0, k0, (const T *)E, wb);
         }
+        // trailing columns: block permutation + block solve, then the update with K = 128
+        // (or 64 for a last block of one panel)
+        const int tiles = (ncol + kBC - 1) / kBC;
+        hipLaunchKernelGGL((k_blocku<TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, k0, 0,
+                           tiles, E, wb);
+        update(kNBO, 0, maxm - k0, ncol);
     }
     return (int)hipGetLastError();
 }
@@ -1318,8 +1437,9 @@ static void run_forward_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int
     const DevMesh &dm = ctx->dm;
     const int tn = (rhs_cols + kTN - 1) / kTN;
     for (int k0 = 0; k0 < maxn; k0 += kNBO) {
-        hipLaunchKernelGGL((k_rowperm<2, TAG, T>), dim3((rhs_cols + kRPC - 1) / kRPC, ne), dim3(256), 0, s, dm, sd, e0,
-                           k0, 0, 1, E, block_ws(ws, k0));
+        const int tiles = (rhs_cols + kBC - 1) / kBC;
+        hipLaunchKernelGGL((k_blocku<TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, k0, 1,
+                           tiles, E, block_ws(ws, k0));
         const int rows = maxn - k0 - kNBO;
         if (rows > 0) {
             const int tm = (rows + kTM - 1) / kTM;
