@@ -25,7 +25,7 @@
 //   k_rowperm    within the block: applies panel a's permutation to panel b's
 //                columns and forms its U rows; applies panel b's permutation
 //                to panel a's L
-//   k_linv128    the (2,1) block of the 128-row unit lower triangle's inverse
+//   k_inv128     the off-diagonal blocks of the 128-row triangles' inverses
 //   k_blocku     trailing columns: the block's net row permutation and
 //                U12 = L11^{-1} P A12 as one triangular product on matrix cores
 //   k_update     A22 -= L21 U12 on matrix cores (16x16x4): first over the second
@@ -81,13 +81,14 @@ static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptio
 // displaced rows, [1 .. W] source row of each top row, then (dst, src) pairs.
 constexpr int kPerm64 = 1 + kNB + 2 * kNB;
 constexpr int kPerm128 = 1 + kNBO + 2 * kNBO;
-// Workspace of one element and one 128-column block: values [5][64*64] (L^{-1}
-// of panels 0, 1, then U^{-1} of panels 0, 1, then the block Lc of the 128-row
-// inverse, below), then ints: piv[128] | perm of panel 0 | perm of panel 1 |
-// perm of the 128 block.  The FP64 path reuses one block's worth per element;
-// the mixed path keeps every block (its solves replay them).
-constexpr int kWsDbl = 5 * kNB * kNB;
-constexpr int kWsLc = 4 * kNB * kNB;
+// Workspace of one element and one 128-column block: values [6][64*64] (L^{-1}
+// of panels 0, 1, then U^{-1} of panels 0, 1, then the off-diagonal blocks Lc
+// and Uc of the 128-row inverses, see k_inv128), then ints: piv[128] | perm of
+// panel 0 | perm of panel 1 | perm of the 128 block.  The FP64 path reuses one
+// block's worth per element; the mixed path keeps every block (its solves
+// replay them).
+constexpr int kWsDbl = 6 * kNB * kNB;
+constexpr int kWsLc = 4 * kNB * kNB, kWsUc = 5 * kNB * kNB;
 constexpr int kWsPiv = 0, kWsPerm0 = kNBO, kWsPerm1 = kWsPerm0 + kPerm64, kWsPerm128 = kWsPerm1 + kPerm64;
 constexpr int kWsInt = kWsPerm128 + kPerm128;
 
@@ -698,14 +699,16 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
     }
 }
 
-// ------------------------------------------- 128-row block forward solve
-// The unit lower triangle of a 128-column block (panels a and b) has the inverse
-// [[La^{-1}, 0], [Lc, Lb^{-1}]], Lc = -Lb^{-1} L_ba La^{-1}.  k_linv128 forms Lc
-// once per element, after panel b's swaps have reached L_ba (rows base+64..,
-// columns base..base+63 of E), and records it in the block's workspace.
+// ------------------------------------------------ 128-row block inverses
+// The unit lower and the upper triangle of a 128-column block (panels a and b)
+// have the inverses [[La^{-1}, 0], [Lc, Lb^{-1}]], Lc = -Lb^{-1} L_ba La^{-1},
+// and [[Ua^{-1}, Uc], [0, Ub^{-1}]], Uc = -Ua^{-1} U_ab Ub^{-1}.  k_inv128 forms
+// Lc and Uc once per element, after panel b's swaps have reached L_ba (rows
+// base+64.., columns base..base+63 of E); U_ab (rows base.., columns base+64..)
+// is final once panel a's U rows are formed.  Both go to the block's workspace.
 template <int TAG, typename T>
-__global__ void __launch_bounds__(256) k_linv128(DevMesh dm, SysDesc sd, int e0, int k0,
-                                                 const T *__restrict__ Ebase, WS<T> ws) {
+__global__ void __launch_bounds__(256) k_inv128(DevMesh dm, SysDesc sd, int e0, int k0, const T *__restrict__ Ebase,
+                                                WS<T> ws) {
     typedef typename MF<T>::acc_t acc_t;
     const int e = e0 + blockIdx.x;
     const ElemDims dd = elem_dims(dm, sd, e);
@@ -716,27 +719,35 @@ __global__ void __launch_bounds__(256) k_linv128(DevMesh dm, SysDesc sd, int e0,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ T sL[kNB][kNB + 1], sR[kNB][kNB + 1];
     T *wd = ws.d + (int64_t)blockIdx.x * ws.ds;
-    for (int t = tid; t < kNB * kNB; t += 256) {
-        const int r = t >> 6, c = t & 63;
-        sL[r][c] = (r < nb1) ? E[(int64_t)(k0 + kNB + r) * ld + k0 + c] : T(0);
-        sR[r][c] = wd[t];
-    }
-    __syncthreads();
     acc_t acc[4];
-    mfma_64x64<T>(sL, sR, acc, lane, wave);  // L_ba La^{-1}
-    __syncthreads();
+    // -(F G H) for 64 x 64 blocks: F from the workspace slot f_slot, G from E at
+    // (g_row, g_col) with rows (or columns) >= nb1 zero, H from slot h_slot;
+    // the result goes to slot out.
+    auto triple = [&](int f_slot, int g_row, int g_col, bool g_rows, int h_slot, int out) {
+        for (int t = tid; t < kNB * kNB; t += 256) {
+            const int r = t >> 6, c = t & 63;
+            sL[r][c] = ((g_rows ? r : c) < nb1) ? E[(int64_t)(g_row + r) * ld + g_col + c] : T(0);
+            sR[r][c] = wd[h_slot + t];
+        }
+        __syncthreads();
+        mfma_64x64<T>(sL, sR, acc, lane, wave);  // G H
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sR[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
-    for (int t = tid; t < kNB * kNB; t += 256) sL[t >> 6][t & 63] = wd[kNB * kNB + t];
-    __syncthreads();
-    mfma_64x64<T>(sL, sR, acc, lane, wave);  // Lb^{-1} L_ba La^{-1}
+            for (int q = 0; q < 4; ++q) sR[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
+        for (int t = tid; t < kNB * kNB; t += 256) sL[t >> 6][t & 63] = wd[f_slot + t];
+        __syncthreads();
+        mfma_64x64<T>(sL, sR, acc, lane, wave);  // F (G H)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            wd[kWsLc + (16 * wave + MF<T>::rowof(lane, q)) * kNB + 16 * j + (lane & 15)] = -acc[j][q];
+            for (int q = 0; q < 4; ++q)
+                wd[out + (16 * wave + MF<T>::rowof(lane, q)) * kNB + 16 * j + (lane & 15)] = -acc[j][q];
+        __syncthreads();
+    };
+    triple(kNB * kNB, k0 + kNB, k0, true, 0, kWsLc);                     // Lc = -Lb^{-1} L_ba La^{-1}
+    triple(2 * kNB * kNB, k0, k0 + kNB, false, 3 * kNB * kNB, kWsUc);    // Uc = -Ua^{-1} U_ab Ub^{-1}
 }
 
 // One 32-column tile of the columns right of a block of nrows = min(128, n - k0)
@@ -854,10 +865,9 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
 //              [k0+K, ncols)  (the LU's trailing update)
 //   kRangeFwd: rows [k0+K, n), columns [n, ncols)  (forward substitution of the
 //              right-hand columns)
-//   kRangeBwd: rows [0, k0), columns [n, ncols)    (back substitution: U12 X2)
 // 128 x 128 tile per workgroup, K in chunks of 16 (FP64) or 32 (FP32) values
 // double-buffered through LDS, matrix cores; C is read before the K loop.
-constexpr int kRangeLU = 0, kRangeFwd = 1, kRangeBwd = 2;
+constexpr int kRangeLU = 0, kRangeFwd = 1;
 constexpr int kTM = 128, kTN = 128;
 template <typename T> struct UpdCfg {
     static constexpr int V = MF<T>::V;
@@ -889,10 +899,8 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     int rbeg, rend, cbeg, cend;
     if (RANGE == kRangeLU) {
         rbeg = k0 + K; rend = dd.mrows; cbeg = k0 + K; cend = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
-    } else if (RANGE == kRangeFwd) {
-        rbeg = k0 + K; rend = dd.n; cbeg = dd.n; cend = dd.ncols;
     } else {
-        rbeg = 0; rend = k0; cbeg = dd.n; cend = dd.ncols;
+        rbeg = k0 + K; rend = dd.n; cbeg = dd.n; cend = dd.ncols;
     }
     const int r0 = rbeg + (t / tiles_n) * kTM;
     const int c0 = cbeg + (t % tiles_n) * kTN;
@@ -1053,70 +1061,202 @@ __global__ void k_zero_int(int *p, int n) {
     if (i < n) p[i] = 0;
 }
 
-// ---------------------------------------------------- mixed precision only
-// Back substitution of one 128-row block on the right-hand columns:
-// X_b = U_b^{-1} Y_b, Y_a -= U_ab X_b, X_a = U_a^{-1} Y_a (U_a, U_b: the diagonal
-// 64-blocks, U_ab the block above U_b), in place.  One workgroup per
-// (64-column tile, element).
-template <int TAG, typename T>
-__global__ void __launch_bounds__(256) k_bsolve(DevMesh dm, SysDesc sd, int e0, int k0, T *__restrict__ Ebase,
-                                                WS<T> ws) {
+// ------------------------------------------------------- back substitution
+// Left-looking back substitution U X = Y on the right-hand columns n.., one
+// 128-row block [k0, k0 + nb) per launch, the blocks below already solved:
+// T = Y_blk - U[blk, k0+nb .. n) X[k0+nb .. n) on matrix cores (as k_update,
+// with K = n - k0 - nb), then X_blk = U_blk^{-1} T with the recorded inverse
+// [[Ua^{-1}, Uc], [0, Ub^{-1}]]: zero blocks skipped, wave w takes the 16-row
+// blocks w and 7 - w (equal work), T passes through LDS in two 64-column
+// halves.  One workgroup per (128-column tile, element), an element's tiles on
+// one XCD.  In place.
+template <typename T, int TAG>
+__global__ void __launch_bounds__(256, 2) k_lbsolve(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int tiles_n,
+                                                    T *__restrict__ Ebase, WS<T> ws) {
+    typedef UpdCfg<T> C;
+    typedef typename MF<T>::v16 v16;
     typedef typename MF<T>::acc_t acc_t;
-    const int e = e0 + blockIdx.y;
+    const int total = ne * tiles_n;
+    const int per_xcd = (total + 7) / 8;
+    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= total) return;
+    const int el = w / tiles_n;
+    const int e = e0 + el;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
-    const int nbo = min(kNBO, dd.n - k0);
-    const int c0 = dd.n + blockIdx.x * 64;
-    if (c0 >= dd.ncols) return;
+    const int nb = min(kNBO, dd.n - k0);
+    const int kb = k0 + nb;  // first row (and column) of the solved part
+    const int K = dd.n - kb;
+    const int r0 = k0, rend = kb;
+    const int c0 = dd.n + (w % tiles_n) * kTN, cend = dd.ncols;
+    if (c0 >= cend) return;  // uniform per block
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
+    const T *wd = ws.d + (int64_t)el * ws.ds;
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ T sX[kNBO][65];
-    __shared__ T sM[kNB][kNB + 1];
-    for (int t = tid; t < kNBO * 64; t += 256) {
-        const int r = t >> 6, c = t & 63;
-        sX[r][c] = (r < nbo && c0 + c < dd.ncols) ? E[(int64_t)(k0 + r) * ld + c0 + c] : T(0);
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    // LDS: the double-buffered operand chunks, later the 128 x 64 half of T
+    constexpr int kStageA = 2 * kTM * C::SA, kStageB = 2 * C::KC * C::SB, kHalfT = kNBO * 65;
+    constexpr int kWords = (kStageA + kStageB > kHalfT) ? kStageA + kStageB : kHalfT;
+    __shared__ __attribute__((aligned(16))) T smem[kWords];
+    T (*sA)[kTM][C::SA] = reinterpret_cast<T (*)[kTM][C::SA]>(smem);
+    T (*sB)[C::KC][C::SB] = reinterpret_cast<T (*)[C::KC][C::SB]>(smem + kStageA);
+    T (*sT)[65] = reinterpret_cast<T (*)[65]>(smem);
+    const int ar = tid >> 3, ak = (tid & 7) * C::V;
+    const int bk = tid / C::LPK, bc = (tid % C::LPK) * C::V;
+    // T = Y - U_right X_below: operands as in k_update (16-byte loads from clamped
+    // in-range addresses, out-of-range entries replaced by 0; K and the column
+    // offsets are multiples of V)
+    constexpr bool kOntoC = sizeof(T) == 8;
+    acc_t acc[4][4];
+    acc_t cpre[kOntoC ? 1 : 4][4];
+    const bool full = (r0 + kTM <= rend) && (c0 + kTN <= cend);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + wr + 16 * bi + MF<T>::rowof(lane, j);
+            const T *row = E + (int64_t)min(r, rend - 1) * ld + c0 + wc + (lane & 15);
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const bool ok = full || (r < rend && c0 + wc + 16 * bj + (lane & 15) < cend);
+                const T c = ok ? row[16 * bj] : T(0);
+                if constexpr (kOntoC) {
+                    acc[bi][bj][j] = c;
+                } else {
+                    cpre[bi][bj][j] = c;
+                    acc[bi][bj][j] = T(0);
+                }
+            }
+        }
+    if (K > 0) {
+        const T *arow[4];
+        bool aok[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = r0 + 32 * q + ar;
+            aok[q] = row < rend;
+            arow[q] = E + (int64_t)min(row, rend - 1) * ld + kb;
+        }
+        const int bcol = c0 + bc;
+        const int bcolc = min(bcol, (cend - 1) & ~(C::V - 1));
+        auto load_chunk = [&](int kc, v16 *ra, v16 *rb) {
+            const int gk = kc + ak;
+            const int gkc = min(gk, (K - 1) & ~(C::V - 1));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const v16 v = *(const v16 *)(arow[q] + gkc);
+#pragma unroll
+                for (int i = 0; i < C::V; ++i) ra[q][i] = (aok[q] && gk + i < K) ? v[i] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gk2 = kc + C::KPQ * q + bk;
+                const bool k2ok = gk2 < K;
+                const v16 v = *(const v16 *)(E + (int64_t)(kb + min(gk2, K - 1)) * ld + bcolc);
+#pragma unroll
+                for (int i = 0; i < C::V; ++i) rb[q][i] = (k2ok && bcol + i < cend) ? v[i] : T(0);
+            }
+        };
+        auto store_chunk = [&](int buf, const v16 *ra, const v16 *rb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                *(v16 *)&sA[buf][32 * q + ar][ak] = kOntoC ? -ra[q] : ra[q];
+                *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = rb[q];
+            }
+        };
+        v16 ra[4], rb[4];
+        load_chunk(0, ra, rb);
+        store_chunk(0, ra, rb);
+        __syncthreads();
+        const int nchunks = (K + C::KC - 1) / C::KC;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nchunks) load_chunk((ch + 1) * C::KC, ra, rb);
+#pragma unroll
+            for (int kk = 0; kk < C::KC; kk += 4) {
+                T av[4], bv[4];
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][wr + 16 * bi + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][kk + (lane >> 4)][wc + 16 * bj + (lane & 15)];
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<T>::mfma(av[bi], bv[bj], acc[bi][bj]);
+            }
+            if (ch + 1 < nchunks) {
+                store_chunk(buf ^ 1, ra, rb);
+                __syncthreads();
+            }
+        }
     }
-    const T *ud = ws.d + (int64_t)blockIdx.y * ws.ds;
-    acc_t acc[4];
-    if (nbo > kNB) {
-        for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = ud[3 * kNB * kNB + t];
-        __syncthreads();
-        mfma_64x64<T>(sM, (const T (*)[65])(&sX[kNB][0]), acc, lane, wave);
-        __syncthreads();
+    if constexpr (!kOntoC) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                sX[kNB + 16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
-        for (int t = tid; t < kNB * kNB; t += 256) {
-            const int r = t >> 6, c = t & 63;
-            sM[r][c] = (kNB + c < nbo) ? E[(int64_t)(k0 + r) * ld + k0 + kNB + c] : T(0);
+            for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = cpre[bi][bj] - acc[bi][bj];
+    }
+    // X_blk = U_blk^{-1} T, 64 columns at a time (rows >= nb of T are zero)
+    const int kq = lane >> 4, cl = lane & 15;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+        if (wc == 64 * h) {
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) sT[wr + 16 * bi + MF<T>::rowof(lane, j)][16 * bj + cl] = acc[bi][bj][j];
         }
         __syncthreads();
-        mfma_64x64<T>(sM, (const T (*)[65])(&sX[kNB][0]), acc, lane, wave);
-        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int hh = 0; hh < 2; ++hh) {
+            const int rb = hh == 0 ? wave : 7 - wave;
+            if (16 * rb >= nb) continue;  // uniform per wave
+            acc_t o[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sX[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] -= acc[j][q];
-    }
-    __syncthreads();
-    for (int t = tid; t < kNB * kNB; t += 256) sM[t >> 6][t & 63] = ud[2 * kNB * kNB + t];
-    __syncthreads();
-    mfma_64x64<T>(sM, sX, acc, lane, wave);
-    __syncthreads();
+            for (int j = 0; j < 4; ++j) o[j] = (acc_t){T(0), T(0), T(0), T(0)};
+            const int r = 16 * rb + cl;
+            if (rb < 4) {
+                const T *ua = wd + 2 * kNB * kNB + r * kNB + kq;  // Ua^{-1}
+#pragma unroll 4
+                for (int kk = 16 * rb; kk < kNB; kk += 4) {
+                    const T a = ua[kk];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < 4; ++j) o[j] = MF<T>::mfma(a, sT[kk + kq][16 * j + cl], o[j]);
+                }
+                if (nb > kNB) {
+                    const T *uc = wd + kWsUc + r * kNB + kq;  // Uc
+#pragma unroll 4
+                    for (int kk = 0; kk < kNB; kk += 4) {
+                        const T a = uc[kk];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sX[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
-    __syncthreads();
-    for (int t = tid; t < nbo * 64; t += 256) {
-        const int r = t >> 6, c = t & 63;
-        if (c0 + c < dd.ncols) E[(int64_t)(k0 + r) * ld + c0 + c] = sX[r][c];
+                        for (int j = 0; j < 4; ++j) o[j] = MF<T>::mfma(a, sT[kNB + kk + kq][16 * j + cl], o[j]);
+                    }
+                }
+            } else {
+                const T *ub = wd + 3 * kNB * kNB + (r - kNB) * kNB + kq;  // Ub^{-1}
+#pragma unroll 4
+                for (int kk = 16 * (rb - 4); kk < kNB; kk += 4) {
+                    const T a = ub[kk];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) o[j] = MF<T>::mfma(a, sT[kNB + kk + kq][16 * j + cl], o[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rr = 16 * rb + MF<T>::rowof(lane, q), c = c0 + 64 * h + 16 * j + cl;
+                    if (rr < nb && c < cend) E[(int64_t)(k0 + rr) * ld + c] = o[j][q];
+                }
+        }
     }
 }
 
+// ---------------------------------------------------- mixed precision only
 __device__ inline void mixed_dims(const DevMesh &dm, int e, int &n, int &f, int64_t &ld, int64_t &ldx) {
     const int p = dm.elem_p[e];
     n = 20 * (p + 1) * (p + 1) * (p + 1);
@@ -1365,7 +1505,7 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
             update(kNB, kNBO, maxm - k0, kNB);
             panel(k0 + kNB, 1);
             hipLaunchKernelGGL((k_rowperm<1, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, E, wb);
-            hipLaunchKernelGGL((k_linv128<TAG, T>), dim3(ne), dim3(256), 0, s, dm, sd, e0, k0, (const T *)E, wb);
+            hipLaunchKernelGGL((k_inv128<TAG, T>), dim3(ne), dim3(256), 0, s, dm, sd, e0, k0, (const T *)E, wb);
         }
         // trailing columns: block permutation + block solve, then the update with K = 128
         // (or 64 for a last block of one panel)
@@ -1412,21 +1552,16 @@ template <typename T> static WS<T> block_ws(WS<T> ws, int k0) {
 }
 
 // Back substitution U X = Y on the right-hand columns n .. ncols of factored
-// systems (the per-block records in ws kept by run_lu with persist), in place.
+// systems (the per-block records in ws kept by run_lu with persist), in place,
+// from the last 128-row block up.
 template <typename T, int TAG>
 static void run_back_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, WS<T> ws, int maxn,
                            int rhs_cols, hipStream_t s) {
     const DevMesh &dm = ctx->dm;
     const int tn = (rhs_cols + kTN - 1) / kTN;
-    for (int k0 = (maxn - 1) / kNBO * kNBO; k0 >= 0; k0 -= kNBO) {
-        hipLaunchKernelGGL((k_bsolve<TAG, T>), dim3((rhs_cols + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, k0, E,
+    for (int k0 = (maxn - 1) / kNBO * kNBO; k0 >= 0; k0 -= kNBO)
+        hipLaunchKernelGGL((k_lbsolve<T, TAG>), dim3((ne * tn + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, k0, tn, E,
                            block_ws(ws, k0));
-        if (k0 > 0) {
-            const int tm = (k0 + kTM - 1) / kTM;
-            hipLaunchKernelGGL((k_update<T, TAG, kRangeBwd>), dim3((ne * tm * tn + 7) / 8 * 8), dim3(256), 0, s, dm, sd,
-                               e0, ne, k0, kNBO, 0, tm, tn, E);
-        }
-    }
 }
 
 // Forward substitution L Y = P R of new right-hand columns, replaying the
