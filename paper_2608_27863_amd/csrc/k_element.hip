@@ -576,65 +576,111 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
     }
 }
 
-// Trace rows of local face lf: [C | D | R_uh] rows of this element's side.
+// Trace rows of local face lf: [C | D | R_uh] rows of this element's side, one
+// workgroup per (face, element).  Only the columns of the face's own nodes (C,
+// not on a Dirichlet face), of the face's trace block (D) and the residual
+// column are nonzero.  A table maps every column once to its basis function (or
+// to zero); each pass forms, for kTR rows (c, a), the weights
+// w(slot, s) = coefficient(c, slot)(s) mu_a(s) at the face's Gauss points, so
+// that a nonzero entry is one dot product over the Gauss points with phi_k(s)
+// (C) or mu_b(s) (D), and a row is written in one coalesced sweep.
+constexpr int kTR = 4;                              // trace rows per pass
+constexpr int kNqfMax = kNQ * kNQ, kNfpMax = kP1 * kP1;
+constexpr int kLdMax = (20 * kP1 * kP1 * kP1 + 30 * kNfpMax + 1 + 7) / 8 * 8;
+
 __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
                                                              double *__restrict__ Ebase) {
     const int e = e0 + blockIdx.y, lf = blockIdx.x;
     const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
     const int *toff = dm.toff + 7 * e;
     const int n = 20 * Np, f = toff[6];
-    const int64_t ld = e_ld(n, f);
+    const int ld = (int)e_ld(n, f);
     double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
     const double *qpe = qp + (dm.qp_off[e] - dm.qp_off[e0]);
     const int tid = threadIdx.x;
     __shared__ double sLf[6][30], sMf[6][30];
     __shared__ int sPf[6], sNqf[6];
     __shared__ int64_t sFbase[6];
+    __shared__ double sPhi[kNfpMax][kNqfMax], sMu[kNfpMax][kNqfMax];
+    __shared__ double sW[kTR][26][kNqfMax];
+    __shared__ int sMap[kLdMax];
     load_face_tables(dm, e, p, Nq, sLf, sMf, sPf, sNqf, sFbase);
     __syncthreads();
-    auto phi_face = [&](int l, int a0, int a1, int s) {
-        const int nqf1 = sPf[l] + 2;
-        return sLf[l][a0 * nqf1 + (s % nqf1)] * sLf[l][a1 * nqf1 + (s / nqf1)];
-    };
-    auto mu_face = [&](int l, int b, int s) {
-        const int pf1 = sPf[l] + 1, nqf1 = sPf[l] + 2;
-        return sMf[l][(b % pf1) * nqf1 + (s % nqf1)] * sMf[l][(b / pf1) * nqf1 + (s / nqf1)];
-    };
-    const int pf1 = sPf[lf] + 1, Nfp = pf1 * pf1, Nqf = sNqf[lf];
+    const int pf1 = sPf[lf] + 1, nqf1 = pf1 + 1, Nfp = pf1 * pf1, Nqf = sNqf[lf];
     const int F = dm.elem_face[6 * e + lf], bc = dm.face_bc[F];
     const double *fb = qpe + sFbase[lf];
     const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
     double *Et = E + (int64_t)(n + toff[lf]) * ld;
     const int nrow = 5 * Nfp;
-    for (int t = tid; t < nrow * (int)ld; t += blockDim.x) {
-        const int row = t / (int)ld, col = t % (int)ld;
-        const int c = row / Nfp, a = row % Nfp;
-        double v = 0.0;
+    // element basis phi_k and trace basis mu_b at the face's Gauss points
+    for (int t = tid; t < kNfpMax * Nqf; t += blockDim.x) {
+        const int k = t / Nqf, sq = t % Nqf, s0 = sq % nqf1, s1 = sq / nqf1;
+        sPhi[k][sq] = (k < p1 * p1) ? sLf[lf][(k % p1) * nqf1 + s0] * sLf[lf][(k / p1) * nqf1 + s1] : 0.0;
+        sMu[k][sq] = (k < Nfp) ? sMf[lf][(k % pf1) * nqf1 + s0] * sMf[lf][(k / pf1) * nqf1 + s1] : 0.0;
+    }
+    // column map: -1 zero; (0, slot, ka0 + p1 ka1) C; (1, cp, b) D; (2) residual
+    for (int col = tid; col < ld; col += blockDim.x) {
+        int code = -1;
         if (col < n) {
             const int sblk = col / Np, k = col % Np;
             int ka0, ka1;
             if (!bc && on_face(k, p1, lf, ka0, ka1)) {
                 const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
-                const double *cf = fb + (int64_t)(25 * c + slot) * Nqf;
-                for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * phi_face(lf, ka0, ka1, s);
+                code = (slot << 8) | (ka0 + p1 * ka1);
             }
         } else if (col < n + f) {
             const int cc = col - n;
             if (cc >= toff[lf] && cc < toff[lf + 1]) {
                 const int cp = (cc - toff[lf]) / Nfp, b = (cc - toff[lf]) % Nfp;
-                if (bc) {
-                    if (cp == c)
-                        for (int s = 0; s < Nqf; ++s) v += fgl[3 * Nqf + s] * mu_face(lf, a, s) * mu_face(lf, b, s);
-                } else {
-                    const double *cf = fb + (int64_t)(25 * c + 20 + cp) * Nqf;
-                    for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s) * mu_face(lf, b, s);
-                }
+                code = (1 << 16) | (cp << 8) | b;
             }
         } else if (col == n + f) {
-            const double *cf = fb + (int64_t)((bc ? 130 : 125) + c) * Nqf;
-            for (int s = 0; s < Nqf; ++s) v += cf[s] * mu_face(lf, a, s);
+            code = 2 << 16;
         }
-        Et[(int64_t)row * ld + col] = v;
+        sMap[col] = code;
+    }
+    for (int r0 = 0; r0 < nrow; r0 += kTR) {
+        __syncthreads();
+        // weights of rows r0 .. r0+kTR-1: slots 0..24 (C by column field, D by
+        // trace component), 25 the residual column
+        for (int t = tid; t < kTR * 26 * Nqf; t += blockDim.x) {
+            const int rr = t / (26 * Nqf), rem = t % (26 * Nqf), slot = rem / Nqf, sq = rem % Nqf;
+            const int row = r0 + rr;
+            double w = 0.0;
+            if (row < nrow) {
+                const int c = row / Nfp, a = row % Nfp;
+                const double mu = sMu[a][sq];
+                if (slot == 25)
+                    w = fb[(int64_t)((bc ? 130 : 125) + c) * Nqf + sq] * mu;
+                else if (bc)
+                    w = (slot == 20 + c) ? fgl[3 * Nqf + sq] * mu : 0.0;
+                else
+                    w = fb[(int64_t)(25 * c + slot) * Nqf + sq] * mu;
+            }
+            sW[rr][slot][sq] = w;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int rr = 0; rr < kTR; ++rr) {
+            const int row = r0 + rr;
+            if (row >= nrow) break;
+            double *dst = Et + (int64_t)row * ld;
+            for (int col = tid; col < ld; col += blockDim.x) {
+                const int code = sMap[col];
+                double v = 0.0;
+                if (code >= 0) {
+                    const int kind = code >> 16, x = (code >> 8) & 255, y = code & 255;
+                    if (kind == 0) {
+                        for (int sq = 0; sq < Nqf; ++sq) v += sW[rr][x][sq] * sPhi[y][sq];
+                    } else if (kind == 1) {
+                        for (int sq = 0; sq < Nqf; ++sq) v += sW[rr][20 + x][sq] * sMu[y][sq];
+                    } else {
+                        for (int sq = 0; sq < Nqf; ++sq) v += sW[rr][25][sq];
+                    }
+                }
+                dst[col] = v;
+            }
+        }
     }
 }
 
