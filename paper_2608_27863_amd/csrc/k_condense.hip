@@ -585,6 +585,24 @@ __device__ inline void mfma_64x64(const T (*Ls)[kNB + 1], const T (*X)[65], type
     }
 }
 
+// acc[j] += A[r][k] X[xoff + k][16 j + cl] over k in [k_lo, k_hi) (multiples of
+// 16) for the lane's row r: arow[k] = A[r][k + kq], fragments in matrix-core
+// order (kq = lane / 16, cl = lane % 16), A from the cache, X from LDS.  Four
+// A loads are issued per 16-wide chunk before its products.
+template <typename T, int NJ, int LDX>
+__device__ inline void mfma_rowblock(const T *arow, const T (*X)[LDX], int xoff, int k_lo, int k_hi, int kq, int cl,
+                                     typename MF<T>::acc_t *acc) {
+    for (int kb = k_lo; kb < k_hi; kb += 16) {
+        T a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = arow[kb + 4 * q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::mfma(a[q], X[xoff + kb + 4 * q + kq][16 * j + cl], acc[j]);
+    }
+}
+
 // Multipliers of the trace rows n..n+f-1 in the panel columns [kp, kp+nb):
 // L_C = C_panel U11^{-1} (matrix cores), one workgroup per 64 trace rows.
 template <int TAG, typename T>
@@ -800,12 +818,17 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
     // displaced rows take original top rows, which are rewritten only after the
     // next barrier
     const int nd = sperm[0];
-#pragma unroll 4
-    for (int t = tid; t < nd * kBC; t += 256) {
-        const int d = t / kBC, c = t % kBC;
-        if (c0 + c < c_end) {
-            const int dst = sperm[1 + W + 2 * d], src = sperm[1 + W + 2 * d + 1];
-            E[(int64_t)dst * ld + c0 + c] = E[(int64_t)src * ld + c0 + c];
+    for (int t0 = tid; t0 < nd * kBC; t0 += 4 * 256) {
+        T v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = t0 + 256 * q, d = t / kBC, c = t % kBC;
+            if (t < nd * kBC && c0 + c < c_end) v[q] = E[(int64_t)sperm[1 + W + 2 * d + 1] * ld + c0 + c];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = t0 + 256 * q, d = t / kBC, c = t % kBC;
+            if (t < nd * kBC && c0 + c < c_end) E[(int64_t)sperm[1 + W + 2 * d] * ld + c0 + c] = v[q];
         }
     }
     // U12 = L11^{-1} X
@@ -819,29 +842,11 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
         if (16 * rb >= nrows) continue;  // uniform per wave
         const int r = 16 * rb + cl;
         if (rb < 4) {
-            const T *arow = wd + r * kNB + kq;  // La^{-1}
-#pragma unroll 4
-            for (int kk = 0; kk < 16 * (rb + 1); kk += 4) {
-                const T a = arow[kk];
-#pragma unroll
-                for (int j = 0; j < kBC / 16; ++j) acc[h][j] = MF<T>::mfma(a, sX[kk + kq][16 * j + cl], acc[h][j]);
-            }
+            mfma_rowblock<T, kBC / 16>(wd + r * kNB + kq, sX, 0, 0, 16 * (rb + 1), kq, cl, acc[h]);  // La^{-1}
         } else {
-            const T *crow = wd + kWsLc + (r - kNB) * kNB + kq;  // Lc
-#pragma unroll 4
-            for (int kk = 0; kk < kNB; kk += 4) {
-                const T a = crow[kk];
-#pragma unroll
-                for (int j = 0; j < kBC / 16; ++j) acc[h][j] = MF<T>::mfma(a, sX[kk + kq][16 * j + cl], acc[h][j]);
-            }
-            const T *brow = wd + kNB * kNB + (r - kNB) * kNB + kq;  // Lb^{-1}
-#pragma unroll 4
-            for (int kk = 0; kk < 16 * (rb - 3); kk += 4) {
-                const T a = brow[kk];
-#pragma unroll
-                for (int j = 0; j < kBC / 16; ++j)
-                    acc[h][j] = MF<T>::mfma(a, sX[kNB + kk + kq][16 * j + cl], acc[h][j]);
-            }
+            mfma_rowblock<T, kBC / 16>(wd + kWsLc + (r - kNB) * kNB + kq, sX, 0, 0, kNB, kq, cl, acc[h]);  // Lc
+            mfma_rowblock<T, kBC / 16>(wd + kNB * kNB + (r - kNB) * kNB + kq, sX, kNB, 0, 16 * (rb - 3), kq, cl,
+                                       acc[h]);  // Lb^{-1}
         }
     }
     __syncthreads();
@@ -1220,30 +1225,11 @@ __global__ void __launch_bounds__(256, 2) k_lbsolve(DevMesh dm, SysDesc sd, int 
             for (int j = 0; j < 4; ++j) o[j] = (acc_t){T(0), T(0), T(0), T(0)};
             const int r = 16 * rb + cl;
             if (rb < 4) {
-                const T *ua = wd + 2 * kNB * kNB + r * kNB + kq;  // Ua^{-1}
-#pragma unroll 4
-                for (int kk = 16 * rb; kk < kNB; kk += 4) {
-                    const T a = ua[kk];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) o[j] = MF<T>::mfma(a, sT[kk + kq][16 * j + cl], o[j]);
-                }
-                if (nb > kNB) {
-                    const T *uc = wd + kWsUc + r * kNB + kq;  // Uc
-#pragma unroll 4
-                    for (int kk = 0; kk < kNB; kk += 4) {
-                        const T a = uc[kk];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) o[j] = MF<T>::mfma(a, sT[kNB + kk + kq][16 * j + cl], o[j]);
-                    }
-                }
+                mfma_rowblock<T, 4>(wd + 2 * kNB * kNB + r * kNB + kq, sT, 0, 16 * rb, kNB, kq, cl, o);  // Ua^{-1}
+                if (nb > kNB) mfma_rowblock<T, 4>(wd + kWsUc + r * kNB + kq, sT, kNB, 0, kNB, kq, cl, o);  // Uc
             } else {
-                const T *ub = wd + 3 * kNB * kNB + (r - kNB) * kNB + kq;  // Ub^{-1}
-#pragma unroll 4
-                for (int kk = 16 * (rb - 4); kk < kNB; kk += 4) {
-                    const T a = ub[kk];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) o[j] = MF<T>::mfma(a, sT[kNB + kk + kq][16 * j + cl], o[j]);
-                }
+                mfma_rowblock<T, 4>(wd + 3 * kNB * kNB + (r - kNB) * kNB + kq, sT, kNB, 16 * (rb - 4), kNB, kq, cl,
+                                    o);  // Ub^{-1}
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)
