@@ -365,12 +365,18 @@ __device__ inline void load_face_tables(const DevMesh &dm, int e, int p, int Nq,
 // (L, D: the 1-D basis and its derivative at the Gauss points).  The face terms
 // and the trace columns are 2-D contractions over each face's Gauss points.
 constexpr int kP1 = kMaxP + 1, kNQ = kMaxP + 2;
-constexpr int kNqMax = kNQ * kNQ * kNQ;
 
+// Instantiated per degree PT (LDS sized for it, loop bounds and index arithmetic
+// known at compile time); workgroups of elements of another degree return.
+template <int PT>
 __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
                                                              double *__restrict__ Ebase) {
     const int r = blockIdx.x, e = e0 + blockIdx.y;
-    const int p = dm.elem_p[e], p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
+    if (dm.elem_p[e] != PT) return;
+    constexpr int p = PT, p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
+    // face-term blocks (6 p1^4) and trace-column blocks (5 p1^2 Nfp, face degree up to kMaxP)
+    constexpr int kSF = std::max(6 * p1 * p1 * p1 * p1, 5 * p1 * p1 * kP1 * kP1);
+    constexpr int kSG = std::max(6 * p1 * p1 * kNQ, 5 * p1 * kP1 * kNQ);
     const int *toff = dm.toff + 7 * e;
     const int n = 20 * Np, f = toff[6];
     const int64_t ld = e_ld(n, f);
@@ -382,15 +388,15 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
     const bool qrow = r < 15;
     const int c = qrow ? r / 3 : r - 15, jdir = qrow ? r % 3 : 0;
 
-    __shared__ double sL[kP1][kNQ], sD[kP1][kNQ];
+    __shared__ double sL[p1][nq], sD[p1][nq];
     __shared__ double sLf[6][30], sMf[6][30];
     __shared__ int sPf[6], sNqf[6];
     __shared__ int64_t sFbase[6];
-    __shared__ double sC[4][kNqMax];                        // coefficient fields of one block
-    __shared__ double sT[3][kP1][kNQ * kNQ];                // x stage of one i1 slice
-    __shared__ double sV[2][kP1 * kP1 * kP1][kNQ];          // y stage of one i1 slice
-    __shared__ double sF[6 * kP1 * kP1 * kP1 * kP1];        // face terms / trace-column blocks
-    __shared__ double sG[6 * kP1 * kP1 * kNQ];              // first stage of the 2-D contractions
+    __shared__ double sC[4][Nq];                 // coefficient fields of one block
+    __shared__ double sT[3][p1][nq * nq];        // x stage of one i1 slice
+    __shared__ double sV[2][p1 * p1 * p1][nq];   // y stage of one i1 slice
+    __shared__ double sF[kSF];                   // face terms / trace-column blocks
+    __shared__ double sG[kSG];                   // first stage of the 2-D contractions
     for (int t = tid; t < p1 * nq; t += blockDim.x) {
         sL[t / nq][t % nq] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
         sD[t / nq][t % nq] = dm.tbl[tbl_D(p, t / nq, t % nq)];
@@ -694,7 +700,12 @@ int launch_element_system(const hdg_ctx *ctx, int e0, int ne, const double *Q, c
     hipLaunchKernelGGL(k_qp_volume, dim3(ne), dim3(256), 0, s, dm, P, e0, Q, U, Un, nu, qp);
     hipLaunchKernelGGL(k_qp_face, dim3(6, ne), dim3(64), 0, s, dm, P, e0, Q, U, Uhat, nu, Ub, qp);
     const double *qpc = qp;
-    hipLaunchKernelGGL(k_assemble_field_rows, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    unsigned degrees = 0;
+    for (int e = e0; e < e0 + ne; ++e) degrees |= 1u << ctx->elem_p[e];
+    if (degrees & 2u) hipLaunchKernelGGL(k_assemble_field_rows<1>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    if (degrees & 4u) hipLaunchKernelGGL(k_assemble_field_rows<2>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    if (degrees & 8u) hipLaunchKernelGGL(k_assemble_field_rows<3>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    if (degrees & 16u) hipLaunchKernelGGL(k_assemble_field_rows<4>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
     hipLaunchKernelGGL(k_assemble_trace_rows, dim3(6, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
     return (int)hipGetLastError();
 }
