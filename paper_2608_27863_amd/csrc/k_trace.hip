@@ -328,12 +328,16 @@ __global__ void __launch_bounds__(256) k_combine(const double *__restrict__ V, i
 }
 
 // ------------------------------------------------------------------ recovery
-// y_i = E[i][n+f] + sum_j E[i][n+j] dUh^K_j for i < n   (one wave per row),
-// then (FP64) back substitution with the upper triangle of E's first n
-// columns; dQU = -x.
-constexpr int kRB = 64;
+// y_i = E[i][n+f] + sum_j E[i][n+j] dUh^K_j for i < n, then (FP64) back
+// substitution with the upper triangle of E's first n columns; dQU = -x.  One
+// 1024-thread workgroup per element.  Every row product is one wave reading
+// the row's entries with consecutive lanes (coalesced), four rows in flight
+// per wave, then a shuffle reduction.  The back substitution goes by 64-row
+// blocks: the diagonal block by wave 0 in LDS, then the rows above update
+// with the block's solution.
+constexpr int kRB = 64, kRT = 1024, kRW = kRT / 64;
 
-__global__ void __launch_bounds__(256) k_recover(DevMesh dm, int e0, int backsub, const double *__restrict__ Ebase,
+__global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub, const double *__restrict__ Ebase,
                                                  const double *__restrict__ dUhat, double *__restrict__ dQU) {
     const int e = e0 + blockIdx.x;
     const int p = dm.elem_p[e], Np = (p + 1) * (p + 1) * (p + 1), n = 20 * Np;
@@ -351,12 +355,24 @@ __global__ void __launch_bounds__(256) k_recover(DevMesh dm, int e0, int backsub
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int i = wave; i < n; i += 4) {
-        const double *row = E + (int64_t)i * ld + n;
-        double s = 0.0;
-        for (int j = lane; j < f; j += 64) s += row[j] * sd[j];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) sy[i] = s + row[f];
+    auto wave_sum = [&](double v) {
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        return v;
+    };
+    // y = Y_r + Y_B dUh, four rows per wave at a time
+    for (int i = 4 * wave; i < n; i += 4 * kRW) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j = lane; j < f; j += 64) {
+            const double dj = sd[j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i + q < n) acc[q] += E[(int64_t)(i + q) * ld + n + j] * dj;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0 && i + q < n) sy[i + q] = v + E[(int64_t)(i + q) * ld + n + f];
+        }
     }
     __syncthreads();
     if (backsub) {
@@ -378,12 +394,18 @@ __global__ void __launch_bounds__(256) k_recover(DevMesh dm, int e0, int backsub
                 if (lane < nb) sy[i0 + lane] = yl;
             }
             __syncthreads();
-            // rows above: y[r] -= U[r][i0:i1] x[i0:i1]
-            for (int r = threadIdx.x; r < i0; r += blockDim.x) {
-                const double *row = E + (int64_t)r * ld + i0;
-                double s = sy[r];
-                for (int c = 0; c < nb; ++c) s -= row[c] * sy[i0 + c];
-                sy[r] = s;
+            // rows above: y[r] -= U[r][i0:i1] x[i0:i1], lane c takes column i0 + c
+            const double xl = (lane < nb) ? sy[i0 + lane] : 0.0;
+            for (int r = 4 * wave; r < i0; r += 4 * kRW) {
+                double v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    v[q] = (r + q < i0 && lane < nb) ? E[(int64_t)(r + q) * ld + i0 + lane] * xl : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double t = wave_sum(v[q]);
+                    if (lane == 0 && r + q < i0) sy[r + q] -= t;
+                }
             }
             __syncthreads();
         }
@@ -534,7 +556,7 @@ int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv
 
 int launch_recover(const hdg_ctx *ctx, int prec, int e0, int ne, const double *E, const double *dUhat, double *dQU,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_recover, dim3(ne), dim3(256), 0, s, ctx->dm, e0, prec == HDG_FP64 ? 1 : 0, E, dUhat, dQU);
+    hipLaunchKernelGGL(k_recover, dim3(ne), dim3(kRT), 0, s, ctx->dm, e0, prec == HDG_FP64 ? 1 : 0, E, dUhat, dQU);
     return (int)hipGetLastError();
 }
 
