@@ -26,17 +26,20 @@
 //                columns and forms its U rows; applies panel b's permutation
 //                to panel a's L
 //   k_inv128     the off-diagonal blocks of the 128-row triangles' inverses
-//   k_blocku     trailing columns: the block's net row permutation and
+//   k_blocku     other columns: the block's net row permutation and
 //                U12 = L11^{-1} P A12 as one triangular product on matrix cores
-//   k_update     A22 -= L21 U12 on matrix cores (16x16x4): first over the second
-//                panel's columns (K = 64), then over every trailing column with
-//                K = 128, which halves the trailing-matrix traffic of a 64-wide
+//                (blocks go in pairs: the far columns get one K = 256 update)
+//   k_update     A22 -= L21 U12 on matrix cores (16x16x4): over the second
+//                panel's columns (K = 64), over the second block's columns
+//                (K = 128), then over every column beyond the pair with K = 256,
+//                a quarter of the trailing-matrix traffic of a 64-wide
 //                right-looking update; 128x128 tiles, the tiles of one element
 //                on one XCD (shared L2)
 // then k_extract copies [S^K | g^K] out (column-major).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <climits>
 
 #include "hdg_internal.h"
@@ -727,7 +730,9 @@ __global__ void __launch_bounds__(256) k_rowperm(DevMesh dm, SysDesc sd, int e0,
 template <int TAG, typename T>
 __global__ void __launch_bounds__(256) k_inv128(DevMesh dm, SysDesc sd, int e0, int k0, const T *__restrict__ Ebase,
                                                 WS<T> ws) {
-    typedef typename MF<T>::acc_t acc_t;
+    // products in FP64 whatever T is, rounded to T once (the FP32 path's
+    // explicit blocks then carry one rounding, not three)
+    typedef typename MF<double>::acc_t acc_t;
     const int e = e0 + blockIdx.x;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n || dd.n - k0 <= kNB) return;
@@ -735,7 +740,7 @@ __global__ void __launch_bounds__(256) k_inv128(DevMesh dm, SysDesc sd, int e0, 
     const T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ T sL[kNB][kNB + 1], sR[kNB][kNB + 1];
+    __shared__ double sL[kNB][kNB + 1], sR[kNB][kNB + 1];
     T *wd = ws.d + (int64_t)blockIdx.x * ws.ds;
     acc_t acc[4];
     // -(F G H) for 64 x 64 blocks: F from the workspace slot f_slot, G from E at
@@ -744,42 +749,51 @@ __global__ void __launch_bounds__(256) k_inv128(DevMesh dm, SysDesc sd, int e0, 
     auto triple = [&](int f_slot, int g_row, int g_col, bool g_rows, int h_slot, int out) {
         for (int t = tid; t < kNB * kNB; t += 256) {
             const int r = t >> 6, c = t & 63;
-            sL[r][c] = ((g_rows ? r : c) < nb1) ? E[(int64_t)(g_row + r) * ld + g_col + c] : T(0);
-            sR[r][c] = wd[h_slot + t];
+            sL[r][c] = ((g_rows ? r : c) < nb1) ? (double)E[(int64_t)(g_row + r) * ld + g_col + c] : 0.0;
+            sR[r][c] = (double)wd[h_slot + t];
         }
         __syncthreads();
-        mfma_64x64<T>(sL, sR, acc, lane, wave);  // G H
+        mfma_64x64<double>(sL, sR, acc, lane, wave);  // G H
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sR[16 * wave + MF<T>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
-        for (int t = tid; t < kNB * kNB; t += 256) sL[t >> 6][t & 63] = wd[f_slot + t];
+            for (int q = 0; q < 4; ++q) sR[16 * wave + MF<double>::rowof(lane, q)][16 * j + (lane & 15)] = acc[j][q];
+        for (int t = tid; t < kNB * kNB; t += 256) sL[t >> 6][t & 63] = (double)wd[f_slot + t];
         __syncthreads();
-        mfma_64x64<T>(sL, sR, acc, lane, wave);  // F (G H)
+        mfma_64x64<double>(sL, sR, acc, lane, wave);  // F (G H)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                wd[out + (16 * wave + MF<T>::rowof(lane, q)) * kNB + 16 * j + (lane & 15)] = -acc[j][q];
+                wd[out + (16 * wave + MF<double>::rowof(lane, q)) * kNB + 16 * j + (lane & 15)] = (T)(-acc[j][q]);
         __syncthreads();
     };
     triple(kNB * kNB, k0 + kNB, k0, true, 0, kWsLc);                     // Lc = -Lb^{-1} L_ba La^{-1}
     triple(2 * kNB * kNB, k0, k0 + kNB, false, 3 * kNB * kNB, kWsUc);    // Uc = -Ua^{-1} U_ab Ub^{-1}
 }
 
-// One 32-column tile of the columns right of a block of nrows = min(128, n - k0)
-// pivot columns: X = P A12 (the block's net row permutation: permuted top rows
-// gathered into LDS, displaced rows moved), then U12 = L11^{-1} X in a single
-// product with the recorded inverse.  The zero blocks of the triangle are
-// skipped; wave w takes the 16-row blocks w and 7 - w, whose inner lengths
+// One 32-column tile of a block of nrows = min(128, n - k0) pivot columns
+// applied to other columns: X = P A12 (the block's net row permutation: permuted
+// top rows gathered into LDS, displaced rows moved), then U12 = L11^{-1} X in a
+// single product with the recorded inverse.  The zero blocks of the triangle
+// are skipped; wave w takes the 16-row blocks w and 7 - w, whose inner lengths
 // 16 (w + 1) and 16 (8 - w) give every wave the same work.  L11^{-1} is read
-// from the cache in matrix-core operand order, X from LDS.  rhs = 1: only the
-// right-hand columns n.. (replays the block's forward substitution).  One
-// workgroup per (tile, element); an element's tiles share an XCD.
-template <int TAG, typename T>
-__global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int rhs, int tiles,
-                                                T *__restrict__ Ebase, WS<T> ws) {
+// from the cache in matrix-core operand order, X from LDS.  Columns: from
+// k0 + max(nrows, min(CB, n - k0)) to k0 + min(CW, n - k0) (CW > 0) or to the
+// last column; rhs = 1: the right-hand columns n.. only (replays the block's
+// forward substitution).
+//   MODE 0  as above.
+//   MODE 1  the second block B of a pair (A, B = rows k0-128..k0-1, k0..): the
+//           columns still lack A's update, which is applied to the gathered
+//           rows only, X -= L_A[top rows] U12_A (A's L after B's swaps, A's U
+//           rows of the tile), before the solve.  The displaced rows keep A's
+//           update pending with their L_A rows.
+//   MODE 2  B's swaps on the columns of A's L (k0-128 .. k0-1), no solve.
+// One workgroup per (tile, element); an element's tiles share an XCD.
+template <int MODE, int TAG, typename T>
+__global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int rhs, int CB,
+                                                int CW, int tiles, T *__restrict__ Ebase, WS<T> ws) {
     typedef typename MF<T>::acc_t acc_t;
     const int total = ne * tiles;
     const int per_xcd = (total + 7) / 8;
@@ -789,14 +803,25 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
     const int e = e0 + el;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
-    const int nrows = min(kNBO, dd.n - k0);
-    const int c_end = dd.ncols;
-    const int c0 = (rhs ? dd.n : k0 + nrows) + (w % tiles) * kBC;
+    const int rem = dd.n - k0, nrows = min(kNBO, rem);
+    int c_begin, c_end;
+    if (MODE == 2) {
+        c_begin = k0 - kNBO;
+        c_end = k0;
+    } else if (rhs) {
+        c_begin = dd.n;
+        c_end = dd.ncols;
+    } else {
+        c_begin = k0 + max(nrows, min(CB, rem));
+        c_end = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
+    }
+    const int c0 = c_begin + (w % tiles) * kBC;
     if (c0 >= c_end) return;  // uniform per block
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ T sX[kNBO][kBC + 1];
+    __shared__ T sU[MODE == 1 ? kNBO : 1][kBC + 1];
     __shared__ int sperm[kPerm128];
     const int *wi = ws.i + (int64_t)el * ws.is;
     const T *wd = ws.d + (int64_t)el * ws.ds;
@@ -811,6 +836,7 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
         const int t = tid + 256 * q;
         const int r = t / kBC, c = t % kBC;
         sX[r][c] = (r < nrows && c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : T(0);
+        if (MODE == 1) sU[r][c] = (c0 + c < c_end) ? E[(int64_t)(k0 - kNBO + r) * ld + c0 + c] : T(0);
     }
     // a top row's source may be a displaced row: its old content must be read
     // before the displaced copies overwrite it
@@ -831,8 +857,37 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
             if (t < nd * kBC && c0 + c < c_end) E[(int64_t)sperm[1 + W + 2 * d] * ld + c0 + c] = v[q];
         }
     }
-    // U12 = L11^{-1} X
     const int kq = lane >> 4, cl = lane & 15;
+    if (MODE == 1) {
+        // X -= L_A[k0 + r][k0-128 ..] U12_A, rows of blocks w and 7 - w
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rb = h == 0 ? wave : 7 - wave;
+            if (16 * rb >= nrows) continue;  // uniform per wave
+            acc_t a[kBC / 16];
+#pragma unroll
+            for (int j = 0; j < kBC / 16; ++j) a[j] = (acc_t){T(0), T(0), T(0), T(0)};
+            const int r = min(k0 + 16 * rb + cl, dd.n - 1);
+            mfma_rowblock<T, kBC / 16>(E + (int64_t)r * ld + k0 - kNBO + kq, sU, 0, 0, kNBO, kq, cl, a);
+#pragma unroll
+            for (int j = 0; j < kBC / 16; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rr = 16 * rb + MF<T>::rowof(lane, q);
+                    if (rr < nrows) sX[rr][16 * j + cl] -= a[j][q];
+                }
+        }
+    }
+    if (MODE == 2) {
+        __syncthreads();
+        for (int t = tid; t < nrows * kBC; t += 256) {
+            const int r = t / kBC, c = t % kBC;
+            if (c0 + c < c_end) E[(int64_t)(k0 + r) * ld + c0 + c] = sX[r][c];
+        }
+        return;
+    }
+    if (MODE == 1) __syncthreads();
+    // U12 = L11^{-1} X
     acc_t acc[2][kBC / 16];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -866,13 +921,14 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
 // --------------------------------------------------------- trailing update
 // C -= A B within one system, K = min(KW, n_e - k0) and A = E[rows, k0 .. k0+K),
 // B = E[k0 .. k0+K, cols]:
-//   kRangeLU:  rows [k0+K, mrows), columns [k0+K, k0+min(CW, n_e-k0)) (CW > 0) or
-//              [k0+K, ncols)  (the LU's trailing update)
+//   kRangeLU:  rows [k0+K, mrows), columns from k0 + max(K, min(CB, n_e-k0)) to
+//              k0+min(CW, n_e-k0) (CW > 0) or to ncols  (the LU's trailing update)
 //   kRangeFwd: rows [k0+K, n), columns [n, ncols)  (forward substitution of the
 //              right-hand columns)
 // 128 x 128 tile per workgroup, K in chunks of 16 (FP64) or 32 (FP32) values
 // double-buffered through LDS, matrix cores; C is read before the K loop.
 constexpr int kRangeLU = 0, kRangeFwd = 1;
+constexpr int kFold = 128;  // FP32 products are folded into C every kFold values of K
 constexpr int kTM = 128, kTN = 128;
 template <typename T> struct UpdCfg {
     static constexpr int V = MF<T>::V;
@@ -884,8 +940,8 @@ template <typename T> struct UpdCfg {
 };
 
 template <typename T, int TAG, int RANGE>
-__global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int KW, int CW,
-                                                   int tiles_m, int tiles_n, T *__restrict__ Ebase) {
+__global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int KW, int CB,
+                                                   int CW, int tiles_m, int tiles_n, T *__restrict__ Ebase) {
     typedef UpdCfg<T> C;
     typedef typename MF<T>::v16 v16;
     typedef typename MF<T>::acc_t acc_t;
@@ -903,7 +959,9 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     const int K = min(KW, rem);
     int rbeg, rend, cbeg, cend;
     if (RANGE == kRangeLU) {
-        rbeg = k0 + K; rend = dd.mrows; cbeg = k0 + K; cend = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
+        rbeg = k0 + K; rend = dd.mrows;
+        cbeg = k0 + max(K, min(CB, rem));
+        cend = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
     } else {
         rbeg = k0 + K; rend = dd.n; cbeg = dd.n; cend = dd.ncols;
     }
@@ -1005,6 +1063,19 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<T>::mfma(av[bi], bv[bj], acc[bi][bj]);
+        }
+        if constexpr (!kOntoC) {
+            // FP32: fold the partial product into C every kFold values of K, so the
+            // rounding of each partial sum stays at the scale of 128 products
+            if ((ch + 1) % (kFold / C::KC) == 0 && ch + 1 < nchunks) {
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 4; ++bj) {
+                        cpre[bi][bj] -= acc[bi][bj];
+                        acc[bi][bj] = (acc_t){T(0), T(0), T(0), T(0)};
+                    }
+            }
         }
         if (ch + 1 < nchunks) {
             store_chunk(buf ^ 1, ra, rb);
@@ -1189,6 +1260,18 @@ __global__ void __launch_bounds__(256, 2) k_lbsolve(DevMesh dm, SysDesc sd, int 
                 for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
                     for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<T>::mfma(av[bi], bv[bj], acc[bi][bj]);
+            }
+            if constexpr (!kOntoC) {
+                // FP32: fold the partial product into Y every kFold values of K
+                if ((ch + 1) % (kFold / C::KC) == 0 && ch + 1 < nchunks) {
+#pragma unroll
+                    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 4; ++bj) {
+                            cpre[bi][bj] -= acc[bi][bj];
+                            acc[bi][bj] = (acc_t){T(0), T(0), T(0), T(0)};
+                        }
+                }
             }
             if (ch + 1 < nchunks) {
                 store_chunk(buf ^ 1, ra, rb);
@@ -1452,21 +1535,46 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
 }  // namespace
 
 // Blocked LU of the systems e0..e0+ne-1 described by sd (bordered: trace rows
-// included when maxf_rows > 0).  ws: per-element workspace; with `persist` every
-// 128-column block keeps its own slot (ws strides hold all blocks).
+// included when maxf_rows > 0).  ws: per-element workspace of a pair of
+// 128-column blocks, or with `persist` one per block (ws strides hold all of
+// them).  maxc: most columns of a system; maxrhs: most columns right of the n
+// pivot columns.
+//
+// The blocks go in pairs (A at K0, B at K0 + 128) so that the columns beyond
+// the pair receive one update with K = 256 instead of two with K = 128, which
+// halves the traffic of the trailing matrix:
+//   factor A; U rows and update of B's columns by A only; factor B;
+//   B's swaps on A's L; A's U rows on the far columns; B's U rows on the far
+//   columns (A's update applied to B's gathered rows); far update, K = 256.
 template <typename T, int TAG>
 static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, int *info, WS<T> ws, bool persist,
-                  int maxn, int maxm, int maxc, int maxf_rows, hipStream_t s) {
+                  int maxn, int maxm, int maxc, int maxrhs, int maxf_rows, hipStream_t s) {
     const DevMesh &dm = ctx->dm;
     hipLaunchKernelGGL(k_zero_int, dim3((ne + 255) / 256), dim3(256), 0, s, info + e0, ne);
     const int R = (maxn + kPT - 1) / kPT;
     if (R > 5) return (int)hipErrorInvalidValue;
-    for (int k0 = 0; k0 < maxn; k0 += kNBO) {
+    auto block_ws_of = [&](int bi) {
         WS<T> wb = ws;
-        if (persist) {
-            wb.d += (int64_t)(k0 / kNBO) * kWsDbl;
-            wb.i += (int64_t)(k0 / kNBO) * kWsInt;
-        }
+        const int slot = persist ? bi : (bi & 1);
+        wb.d += (int64_t)slot * kWsDbl;
+        wb.i += (int64_t)slot * kWsInt;
+        return wb;
+    };
+    auto update = [&](int k0, int KW, int CB, int CW, int rows, int cols) {
+        if (rows <= 0 || cols <= 0) return;
+        const int tm = (rows + kTM - 1) / kTM, tn = (cols + kTN - 1) / kTN;
+        const int total = ne * tm * tn;
+        hipLaunchKernelGGL((k_update<T, TAG, kRangeLU>), dim3((total + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne,
+                           k0, KW, CB, CW, tm, tn, E);
+    };
+    auto blocku = [&](auto mode, int k0, const WS<T> &wb, int CB, int CW, int cols) {
+        if (cols <= 0) return;
+        const int tiles = (cols + kBC - 1) / kBC;
+        hipLaunchKernelGGL((k_blocku<decltype(mode)::value, TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s,
+                           dm, sd, e0, ne, k0, 0, CB, CW, tiles, E, wb);
+    };
+    // panels of the 128-column block at k0 and their records
+    auto factor_block = [&](int k0, const WS<T> &wb) {
         auto panel = [&](int kp, int slot) {
             if (R <= 1) hipLaunchKernelGGL((k_panel<1, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
             else if (R <= 2) hipLaunchKernelGGL((k_panel<2, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
@@ -1476,29 +1584,34 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
                 hipLaunchKernelGGL((k_crows<TAG, T>), dim3((maxf_rows + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, kp,
                                    slot, E, wb);
         };
-        auto update = [&](int KW, int CW, int rows, int cols) {
-            if (rows <= 0 || cols <= 0) return;
-            const int tm = (rows + kTM - 1) / kTM, tn = (cols + kTN - 1) / kTN;
-            const int total = ne * tm * tn;
-            hipLaunchKernelGGL((k_update<T, TAG, kRangeLU>), dim3((total + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne,
-                               k0, KW, CW, tm, tn, E);
-        };
-        const int ncol = maxc - k0;
         panel(k0, 0);
         if (maxn - k0 > kNB) {
             // rest of the 128-column block, then its second panel
             hipLaunchKernelGGL((k_rowperm<0, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, kNBO, E, wb);
-            update(kNB, kNBO, maxm - k0, kNB);
+            update(k0, kNB, 0, kNBO, maxm - k0, kNB);
             panel(k0 + kNB, 1);
             hipLaunchKernelGGL((k_rowperm<1, TAG, T>), dim3(kNB / kRPC, ne), dim3(256), 0, s, dm, sd, e0, k0, 0, E, wb);
             hipLaunchKernelGGL((k_inv128<TAG, T>), dim3(ne), dim3(256), 0, s, dm, sd, e0, k0, (const T *)E, wb);
         }
-        // trailing columns: block permutation + block solve, then the update with K = 128
-        // (or 64 for a last block of one panel)
-        const int tiles = (ncol + kBC - 1) / kBC;
-        hipLaunchKernelGGL((k_blocku<TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, k0, 0,
-                           tiles, E, wb);
-        update(kNBO, 0, maxm - k0, ncol);
+    };
+    using M0 = std::integral_constant<int, 0>;
+    using M1 = std::integral_constant<int, 1>;
+    using M2 = std::integral_constant<int, 2>;
+    for (int K0 = 0, pi = 0; K0 < maxn; K0 += 2 * kNBO, ++pi) {
+        const WS<T> wa = block_ws_of(2 * pi), wb = block_ws_of(2 * pi + 1);
+        const bool pairB = maxn - K0 > kNBO;
+        factor_block(K0, wa);
+        if (pairB) {
+            blocku(M0{}, K0, wa, 0, 2 * kNBO, kNBO);
+            update(K0, kNBO, 0, 2 * kNBO, maxm - K0, kNBO);
+            factor_block(K0 + kNBO, wb);
+            blocku(M2{}, K0 + kNBO, wb, 0, 0, kNBO);
+        }
+        // far columns: beyond the pair (the right-hand and trace columns included)
+        const int far = std::max(maxc - K0 - 2 * kNBO, maxrhs);
+        blocku(M0{}, K0, wa, 2 * kNBO, 0, far);
+        if (pairB) blocku(M1{}, K0 + kNBO, wb, kNBO, 0, far);
+        update(K0, 2 * kNBO, 2 * kNBO, 0, maxm - K0, far);
     }
     return (int)hipGetLastError();
 }
@@ -1518,8 +1631,9 @@ int launch_condense_fp64(const hdg_ctx *ctx, int e0, int ne, double *E, double *
     chunk_max(ctx, e0, ne, &maxn, &maxf);
     for (int e = e0; e < e0 + ne; ++e) maxm = std::max(maxm, ctx->elem_n[e] + ctx->elem_f[e]);
     const SysDesc sd{0, ctx->dm.E_off};
-    WS<double> ws{(double *)work, (int *)((char *)work + sizeof(double) * (size_t)ne * kWsDbl), kWsDbl, kWsInt};
-    int err = run_lu<double, 0>(ctx, sd, e0, ne, E, info, ws, false, maxn, maxm, maxm + 1, maxf, s);
+    WS<double> ws{(double *)work, (int *)((char *)work + sizeof(double) * (size_t)ne * 2 * kWsDbl), 2 * kWsDbl,
+                  2 * kWsInt};
+    int err = run_lu<double, 0>(ctx, sd, e0, ne, E, info, ws, false, maxn, maxm, maxm + 1, maxf + 1, maxf, s);
     if (err) return err;
     hipLaunchKernelGGL(k_extract, dim3((maxf + 1 + 31) / 32, (maxf + 31) / 32, ne), dim3(256), 0, s, ctx->dm, sd,
                        e0, (const double *)E, SK);
@@ -1528,7 +1642,7 @@ int launch_condense_fp64(const hdg_ctx *ctx, int e0, int ne, double *E, double *
 
 size_t bordered_lu_work(const hdg_ctx *ctx, int ne) {
     (void)ctx;
-    return sizeof(double) * (size_t)ne * kWsDbl + sizeof(int) * (size_t)ne * kWsInt;
+    return 2 * (sizeof(double) * (size_t)ne * kWsDbl + sizeof(int) * (size_t)ne * kWsInt);
 }
 
 template <typename T> static WS<T> block_ws(WS<T> ws, int k0) {
@@ -1551,21 +1665,24 @@ static void run_back_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne
 }
 
 // Forward substitution L Y = P R of new right-hand columns, replaying the
-// recorded permutations block by block.
+// recorded permutations and the pairing of the blocks as the factorisation did.
 template <typename T, int TAG>
 static void run_forward_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, WS<T> ws, int maxn,
                               int rhs_cols, hipStream_t s) {
     const DevMesh &dm = ctx->dm;
     const int tn = (rhs_cols + kTN - 1) / kTN;
-    for (int k0 = 0; k0 < maxn; k0 += kNBO) {
-        const int tiles = (rhs_cols + kBC - 1) / kBC;
-        hipLaunchKernelGGL((k_blocku<TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, k0, 1,
-                           tiles, E, block_ws(ws, k0));
-        const int rows = maxn - k0 - kNBO;
+    const int tiles = (rhs_cols + kBC - 1) / kBC;
+    for (int K0 = 0; K0 < maxn; K0 += 2 * kNBO) {
+        hipLaunchKernelGGL((k_blocku<0, TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, K0, 1,
+                           0, 0, tiles, E, block_ws(ws, K0));
+        if (maxn - K0 > kNBO)
+            hipLaunchKernelGGL((k_blocku<1, TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne,
+                               K0 + kNBO, 1, 0, 0, tiles, E, block_ws(ws, K0 + kNBO));
+        const int rows = maxn - K0 - 2 * kNBO;
         if (rows > 0) {
             const int tm = (rows + kTM - 1) / kTM;
             hipLaunchKernelGGL((k_update<T, TAG, kRangeFwd>), dim3((ne * tm * tn + 7) / 8 * 8), dim3(256), 0, s, dm, sd,
-                               e0, ne, k0, kNBO, 0, tm, tn, E);
+                               e0, ne, K0, 2 * kNBO, 0, 0, tm, tn, E);
         }
     }
 }
@@ -1590,12 +1707,12 @@ int run_asm_inversion(const hdg_ctx *ctx, int prec, void *sys, int *info, void *
     int *wi = (int *)((char *)iwork + ((es * (size_t)ne * nblk * kWsDbl + 255) / 256 * 256));
     if (prec == HDG_FP64) {
         WS<double> ws{(double *)iwork, wi, (int64_t)nblk * kWsDbl, (int64_t)nblk * kWsInt};
-        int err = run_lu<double, 1>(ctx, sd, 0, ne, (double *)sys, info, ws, true, m, m, 2 * m + 1, 0, s);
+        int err = run_lu<double, 1>(ctx, sd, 0, ne, (double *)sys, info, ws, true, m, m, 2 * m + 1, m + 1, 0, s);
         if (err) return err;
         run_back_solve<double, 1>(ctx, sd, 0, ne, (double *)sys, ws, m, m + 1, s);
     } else {
         WS<float> ws{(float *)iwork, wi, (int64_t)nblk * kWsDbl, (int64_t)nblk * kWsInt};
-        int err = run_lu<float, 3>(ctx, sd, 0, ne, (float *)sys, info, ws, true, m, m, 2 * m + 1, 0, s);
+        int err = run_lu<float, 3>(ctx, sd, 0, ne, (float *)sys, info, ws, true, m, m, 2 * m + 1, m + 1, 0, s);
         if (err) return err;
         run_back_solve<float, 3>(ctx, sd, 0, ne, (float *)sys, ws, m, m + 1, s);
     }
@@ -1643,7 +1760,7 @@ int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double
     const dim3 elem_grid(64, ne);
     hipLaunchKernelGGL(k_to32, elem_grid, dim3(256), 0, s, dm, e0, (const double *)E, M);
     // FP32 LU of A with the forward substitution of [B | R_qu] carried along, then X_0
-    int err = run_lu<float, 2>(ctx, sd, e0, ne, M, info, ws, true, maxn, maxn, maxn + maxf + 1, 0, s);
+    int err = run_lu<float, 2>(ctx, sd, e0, ne, M, info, ws, true, maxn, maxn, maxn + maxf + 1, maxf + 1, 0, s);
     if (err) return err;
     back_solve();
     hipLaunchKernelGGL(k_xupdate<0>, elem_grid, dim3(256), 0, s, dm, e0, (const float *)M, X, E);
