@@ -609,6 +609,7 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
     __shared__ int64_t sFbase[6];
     __shared__ double sPhi[kNfpMax][kNqfMax], sMu[kNfpMax][kNqfMax];
     __shared__ double sW[kTR][26][kNqfMax];
+    __shared__ double sK[26][kNqfMax];  // coefficients of the current component c
     __shared__ int sMap[kLdMax];
     load_face_tables(dm, e, p, Nq, sLf, sMf, sPf, sNqf, sFbase);
     __syncthreads();
@@ -645,27 +646,35 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
         }
         sMap[col] = code;
     }
+    // rows go component by component (c = row / Nfp); a component's
+    // coefficients at the Gauss points are staged in LDS once
+    int c_loaded = -1;
     for (int r0 = 0; r0 < nrow; r0 += kTR) {
         __syncthreads();
+        const int c_lo = r0 / Nfp, c_hi = min(r0 + kTR - 1, nrow - 1) / Nfp;
         // weights of rows r0 .. r0+kTR-1: slots 0..24 (C by column field, D by
         // trace component), 25 the residual column
-        for (int t = tid; t < kTR * 26 * Nqf; t += blockDim.x) {
-            const int rr = t / (26 * Nqf), rem = t % (26 * Nqf), slot = rem / Nqf, sq = rem % Nqf;
-            const int row = r0 + rr;
-            double w = 0.0;
-            if (row < nrow) {
-                const int c = row / Nfp, a = row % Nfp;
-                const double mu = sMu[a][sq];
-                if (slot == 25)
-                    w = fb[(int64_t)((bc ? 130 : 125) + c) * Nqf + sq] * mu;
-                else if (bc)
-                    w = (slot == 20 + c) ? fgl[3 * Nqf + sq] * mu : 0.0;
-                else
-                    w = fb[(int64_t)(25 * c + slot) * Nqf + sq] * mu;
+        for (int cc = c_lo; cc <= c_hi; ++cc) {
+            if (cc != c_loaded) {
+                for (int t = tid; t < 26 * Nqf; t += blockDim.x) {
+                    const int slot = t / Nqf, sq = t % Nqf;
+                    double k;
+                    if (slot == 25) k = fb[(int64_t)((bc ? 130 : 125) + cc) * Nqf + sq];
+                    else if (bc) k = (slot == 20 + cc) ? fgl[3 * Nqf + sq] : 0.0;
+                    else k = fb[(int64_t)(25 * cc + slot) * Nqf + sq];
+                    sK[slot][sq] = k;
+                }
+                c_loaded = cc;
+                __syncthreads();
             }
-            sW[rr][slot][sq] = w;
+            for (int t = tid; t < kTR * 26 * Nqf; t += blockDim.x) {
+                const int rr = t / (26 * Nqf), rem = t % (26 * Nqf), slot = rem / Nqf, sq = rem % Nqf;
+                const int row = r0 + rr;
+                if (row < nrow && row / Nfp == cc) sW[rr][slot][sq] = sK[slot][sq] * sMu[row % Nfp][sq];
+                else if (row >= nrow) sW[rr][slot][sq] = 0.0;
+            }
+            __syncthreads();
         }
-        __syncthreads();
 #pragma unroll 1
         for (int rr = 0; rr < kTR; ++rr) {
             const int row = r0 + rr;
