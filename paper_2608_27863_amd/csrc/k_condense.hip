@@ -19,8 +19,9 @@
 // Two-level blocking, all elements of a chunk advancing together.  Per block
 // of kNBO = 128 pivot columns (two panels of kNB = 64):
 //   k_panel      one workgroup per element factors a 64-column panel (8-column
-//                sub-panels held in registers), records its pivots, the net row
-//                permutation, L11^{-1} and U11^{-1}
+//                sub-panels held in registers) in two 32-column halves, records
+//                its pivots, the net row permutation, L11^{-1} and U11^{-1}
+//   k_half       the first half's update of the second half's columns
 //   k_crows      multipliers of the trace rows, L_C = C_panel U11^{-1}
 //   k_rowperm    within the block: applies panel a's permutation to panel b's
 //                columns and forms its U rows; applies panel b's permutation
@@ -180,11 +181,13 @@ __device__ void block_net_perm(int base, int w, const int *piv, int *top_src, in
 // Factor the panel columns [k0, k0+nb) over the pivot rows [k0, n) (the trace
 // rows n.. get their multipliers from k_crows).  Rows are distributed over the
 // threads (row cb + tid + kPT i), kW columns at a time held in registers.  The
-// panel is two halves: sub-panels update the columns of their own half only, and
-// the second half receives the whole first half's update in one pass (which
-// reads and writes the panel's right part far fewer times).
+// panel is two halves factored by two launches (part 1, part 2): sub-panels
+// update the columns of their own half only; part 1 ends with the first half's
+// U12 rows, and the second half receives the whole first half's update from
+// k_half (matrix cores, many workgroups) between the launches, which reads and
+// writes the panel's right part far fewer times.
 template <int R, int TAG, typename T>
-__global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase,
+__global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase, int part,
                                                T *__restrict__ Ebase, WS<T> ws, int *__restrict__ info) {
     typedef typename MF<T>::v2 v2;
     const int e = e0 + blockIdx.x;
@@ -205,8 +208,18 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
     __shared__ int s_piv2[kNBO], s_wcnt[2];
     __shared__ T s_T[kNB][kNB + 1], s_I[kNB][kNB + 1];
     int info_k = 0;
+    // part 1: the first half (ending with its U12 rows), part 2: the second
+    // half and the records; a panel of at most kHalf columns is done by part 1
+    const bool split = nb > kHalf;
+    if (part == 2 && !split) return;
+    int *wi = ws.i + (int64_t)blockIdx.x * ws.is;
+    const int j_begin = (part == 2) ? kHalf : 0, j_end = (part == 1 && split) ? kHalf : nb;
+    if (part == 2) {
+        for (int t = tid; t < kHalf; t += kPT) s_piv[t] = wi[kWsPiv + slot * kNB + t];
+        __syncthreads();
+    }
 
-    for (int j0 = 0; j0 < nb; j0 += kW) {
+    for (int j0 = j_begin; j0 < j_end; j0 += kW) {
         const int w = min(kW, nb - j0), cb = k0 + j0;
         T a[R][kW];
 #pragma unroll
@@ -354,7 +367,7 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
         }
         // sub-panels of the first half update only the first half's columns; the
         // second half receives the first half's update in one pass below
-        const int nrloc = (j0 + w <= kHalf && nb > kHalf) ? kHalf - j0 - w : nright;
+        const int nrloc = (j0 + w <= kHalf && split) ? kHalf - j0 - w : nright;
         if (nrloc > 0) {
             // U of the sub-panel rows in the right columns: unit lower solve
             for (int cidx = tid; cidx < nrloc; cidx += kPT) {
@@ -394,9 +407,10 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
             }
             __syncthreads();
         }
-        if (nb > kHalf && j0 + w == kHalf) {
+        if (split && j0 + w == kHalf) {
             // second half: U12 = L11^{-1} A12 on the top kHalf rows (one thread per
-            // column), then A22 -= L21 U12 for every pivot row below
+            // column); A22 -= L21 U12 for the rows below is k_half's, between the
+            // two launches
             const int nb2 = nb - kHalf;
             for (int t = tid; t < kHalf * kHalf; t += kPT) {
                 const int r = t / kHalf, c = t % kHalf;
@@ -416,41 +430,15 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
                 const int r = t / nb2, c = t % nb2;
                 E[(int64_t)(k0 + r) * ld + k0 + kHalf + c] = s_I[r][c];
             }
-            // A22 -= L21 U12, one pivot row per thread, 8 columns x 8 inner indices
-            // at a time (short loops keep the live registers few)
-#pragma unroll 1
-            for (int r = k0 + kHalf + tid; r < n; r += kPT) {
-                const T *src = E + (int64_t)r * ld + k0;
-                T *row = E + (int64_t)r * ld + k0 + kHalf;
-#pragma unroll 1
-                for (int c8 = 0; c8 < nb2; c8 += 8) {
-                    T v[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = (c8 + q < nb2) ? row[c8 + q] : T(0);
-#pragma unroll 1
-                    for (int kb = 0; kb < kHalf; kb += 8) {
-                        T l8[8];
-#pragma unroll
-                        for (int c = 0; c < 8; c += 2) {
-                            const v2 lv = *(const v2 *)(src + kb + c);
-                            l8[c] = lv.x;
-                            l8[c + 1] = lv.y;
-                        }
-#pragma unroll
-                        for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) v[q] -= l8[kk] * s_I[kb + kk][(c8 + q) & (kHalf - 1)];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (c8 + q < nb2) row[c8 + q] = v[q];
-                }
-            }
-            __syncthreads();
         }
     }
+    if (part == 1 && split) {
+        // first half done: its pivots go to the workspace for the second launch
+        for (int t = tid; t < kHalf; t += kPT) wi[kWsPiv + slot * kNB + t] = s_piv[t];
+        if (tid == 0 && info_k && info[e] == 0) info[e] = info_k;
+        return;
+    }
     // record pivots, the panel's net permutation, L11^{-1} and U11^{-1}
-    int *wi = ws.i + (int64_t)blockIdx.x * ws.is;
     T *wd = ws.d + (int64_t)blockIdx.x * ws.ds;
     for (int t = tid; t < nb; t += kPT) wi[kWsPiv + slot * kNB + t] = s_piv[t];
     {
@@ -604,6 +592,49 @@ __device__ inline void mfma_rowblock(const T *arow, const T (*X)[LDX], int xoff,
 #pragma unroll
             for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::mfma(a[q], X[xoff + kb + 4 * q + kq][16 * j + cl], acc[j]);
     }
+}
+
+// A22 -= L21 U12 between the two halves of the panel at kp: pivot rows
+// kp+32 .. n-1, columns kp+32 .. kp+nb-1, K = 32.  64 rows per workgroup (16
+// per wave), U12 (zero beyond nb) in LDS, L21 fragments from the cache.
+template <int TAG, typename T>
+__global__ void __launch_bounds__(256) k_half(DevMesh dm, SysDesc sd, int e0, int kp, T *__restrict__ Ebase) {
+    typedef typename MF<T>::acc_t acc_t;
+    const int e = e0 + blockIdx.y;
+    const ElemDims dd = elem_dims(dm, sd, e);
+    if (kp >= dd.n) return;
+    const int nb = min(kNB, dd.n - kp);
+    if (nb <= kHalf) return;
+    const int nb2 = nb - kHalf;
+    const int r0 = kp + kHalf + blockIdx.x * 64;
+    if (r0 >= dd.n) return;  // uniform per block
+    T *E = Ebase + (sd.off[e] - sd.off[e0]);
+    const int64_t ld = dd.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kq = lane >> 4, cl = lane & 15;
+    __shared__ T sU[kHalf][kHalf + 1];
+    for (int t = tid; t < kHalf * kHalf; t += 256) {
+        const int r = t / kHalf, c = t % kHalf;
+        sU[r][c] = (c < nb2) ? E[(int64_t)(kp + r) * ld + kp + kHalf + c] : T(0);
+    }
+    __syncthreads();
+    const int rb = r0 + 16 * wave;
+    if (rb >= dd.n) return;  // uniform per wave; no barrier follows
+    acc_t acc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[j] = (acc_t){T(0), T(0), T(0), T(0)};
+    const int ra = min(rb + cl, dd.n - 1);
+    mfma_rowblock<T, 2>(E + (int64_t)ra * ld + kp + kq, sU, 0, 0, kHalf, kq, cl, acc);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = rb + MF<T>::rowof(lane, q), c = 16 * j + cl;
+            if (r < dd.n && c < nb2) {
+                T *dst = E + (int64_t)r * ld + kp + kHalf + c;
+                *dst = *dst - acc[j][q];
+            }
+        }
 }
 
 // Multipliers of the trace rows n..n+f-1 in the panel columns [kp, kp+nb):
@@ -1576,10 +1607,17 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
     // panels of the 128-column block at k0 and their records
     auto factor_block = [&](int k0, const WS<T> &wb) {
         auto panel = [&](int kp, int slot) {
-            if (R <= 1) hipLaunchKernelGGL((k_panel<1, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
-            else if (R <= 2) hipLaunchKernelGGL((k_panel<2, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
-            else if (R <= 3) hipLaunchKernelGGL((k_panel<3, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
-            else hipLaunchKernelGGL((k_panel<5, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, E, wb, info);
+            auto half = [&](int part) {
+                if (R <= 1) hipLaunchKernelGGL((k_panel<1, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, part, E, wb, info);
+                else if (R <= 2) hipLaunchKernelGGL((k_panel<2, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, part, E, wb, info);
+                else if (R <= 3) hipLaunchKernelGGL((k_panel<3, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, part, E, wb, info);
+                else hipLaunchKernelGGL((k_panel<5, TAG, T>), dim3(ne), dim3(kPT), 0, s, dm, sd, e0, kp, slot, k0, part, E, wb, info);
+            };
+            half(1);
+            if (maxn - kp > kHalf)
+                hipLaunchKernelGGL((k_half<TAG, T>), dim3((maxn - kp - kHalf + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0,
+                                   kp, E);
+            half(2);
             if (maxf_rows > 0)
                 hipLaunchKernelGGL((k_crows<TAG, T>), dim3((maxf_rows + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, kp,
                                    slot, E, wb);
