@@ -276,7 +276,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic(f"condense_fp64_{tag}_hbm"),
-                     "kernel": "hdg_condense (per 128-column block: k_panel x2, k_crows, k_rowperm, k_inv128, k_blocku, "
+                     "kernel": "hdg_condense (per pair of 128-column blocks: k_panel, k_half, k_crows, k_rowperm, k_inv128, k_blocku, "
                                "k_update; then k_extract)",
                      "algorithmic": f"{fl:.4e} flop over {ne} elements (LU 2n^3/3 + solve 2n^2(f+1) + "
                                     f"Schur 2fn(f+1) per element)"},
