@@ -684,13 +684,16 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
                 const int code = sMap[col];
                 double v = 0.0;
                 if (code >= 0) {
+                    // unrolled so that the LDS loads of a dot product are in flight together
                     const int kind = code >> 16, x = (code >> 8) & 255, y = code & 255;
-                    if (kind == 0) {
-                        for (int sq = 0; sq < Nqf; ++sq) v += sW[rr][x][sq] * sPhi[y][sq];
-                    } else if (kind == 1) {
-                        for (int sq = 0; sq < Nqf; ++sq) v += sW[rr][20 + x][sq] * sMu[y][sq];
+                    const double *wrow = sW[rr][kind == 0 ? x : (kind == 1 ? 20 + x : 25)];
+                    const double *brow = kind == 0 ? sPhi[y] : sMu[y];
+                    if (kind == 2) {
+#pragma unroll 8
+                        for (int sq = 0; sq < Nqf; ++sq) v += wrow[sq];
                     } else {
-                        for (int sq = 0; sq < Nqf; ++sq) v += sW[rr][25][sq];
+#pragma unroll 8
+                        for (int sq = 0; sq < Nqf; ++sq) v += wrow[sq] * brow[sq];
                     }
                 }
                 dst[col] = v;
