@@ -168,12 +168,16 @@ __global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const T *__rest
 }
 
 // ------------------------------------------------------------- Schwarz apply
+// zloc = S_r^{-1} y_r, y_r gathered from the element's six faces.  One
+// workgroup per (element, 256 rows); the column-major inverse is streamed with
+// consecutive lanes on consecutive rows, eight columns in flight per thread.
 template <typename T>
 __global__ void __launch_bounds__(256) k_asm_local(DevMesh dm, const T *__restrict__ Sinv, const double *__restrict__ r,
                                                    double *__restrict__ zloc) {
     const int e = blockIdx.x;
     const int *to = dm.toff + 7 * e;
     const int f = to[6];
+    if ((int)blockIdx.y * 256 >= f) return;  // uniform per block
     __shared__ double sy[750];
     for (int lf = 0; lf < 6; ++lf) {
         const int F = dm.elem_face[6 * e + lf];
@@ -182,20 +186,19 @@ __global__ void __launch_bounds__(256) k_asm_local(DevMesh dm, const T *__restri
     }
     __syncthreads();
     const T *M = Sinv + dm.asm_off[e];
-    for (int i = threadIdx.x; i < f; i += blockDim.x) {
-        double acc = 0.0;
-        int j = 0;
-        for (; j + 3 < f; j += 4) {
-            const double a0 = (double)M[(int64_t)j * f + i], a1 = (double)M[(int64_t)(j + 1) * f + i];
-            const double a2 = (double)M[(int64_t)(j + 2) * f + i], a3 = (double)M[(int64_t)(j + 3) * f + i];
-            acc += a0 * sy[j];
-            acc += a1 * sy[j + 1];
-            acc += a2 * sy[j + 2];
-            acc += a3 * sy[j + 3];
-        }
-        for (; j < f; ++j) acc += (double)M[(int64_t)j * f + i] * sy[j];
-        zloc[dm.tloc_off[e] + i] = acc;
+    const int i = blockIdx.y * 256 + threadIdx.x;
+    if (i >= f) return;
+    double acc = 0.0;
+    int j = 0;
+    for (; j + 7 < f; j += 8) {
+        double a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = (double)M[(int64_t)(j + q) * f + i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += a[q] * sy[j + q];
     }
+    for (; j < f; ++j) acc += (double)M[(int64_t)j * f + i] * sy[j];
+    zloc[dm.tloc_off[e] + i] = acc;
 }
 
 __global__ void __launch_bounds__(128) k_asm_gather(DevMesh dm, const double *__restrict__ zloc, double *__restrict__ z) {
@@ -471,10 +474,11 @@ int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const doubl
                      hipStream_t s) {
     const DevMesh &dm = ctx->dm;
     double *zloc = (double *)work;
+    const dim3 grid(ctx->n_elem, (ctx->max_f + 255) / 256);
     if (prec == HDG_FP64)
-        hipLaunchKernelGGL(k_asm_local<double>, dim3(ctx->n_elem), dim3(256), 0, s, dm, (const double *)Sinv, r, zloc);
+        hipLaunchKernelGGL(k_asm_local<double>, grid, dim3(256), 0, s, dm, (const double *)Sinv, r, zloc);
     else
-        hipLaunchKernelGGL(k_asm_local<float>, dim3(ctx->n_elem), dim3(256), 0, s, dm, (const float *)Sinv, r, zloc);
+        hipLaunchKernelGGL(k_asm_local<float>, grid, dim3(256), 0, s, dm, (const float *)Sinv, r, zloc);
     hipLaunchKernelGGL(k_asm_gather, dim3(ctx->n_face), dim3(128), 0, s, dm, (const double *)zloc, z);
     return (int)hipGetLastError();
 }
