@@ -113,20 +113,27 @@ __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__rest
 }
 
 // ------------------------------------------------------------- Schwarz setup
-// Systems [[S_r', I], [I, 0]] (row-major, row stride e_ld(m, m)), m = f rounded up to
-// even; for odd f, S_r' = [[S_r, 0], [0, 1]] (one decoupled unknown).
+// Systems [S_r' | I] (m rows, row-major, row stride e_ld(m, m)), m = f rounded up
+// to a multiple of 4; S_r' = [[S_r, 0], [0, I]] (decoupled padding unknowns).
+// One 32 x 32 tile of the system per workgroup: read with consecutive lanes on
+// consecutive rows (the BSR blocks are column-major), written through LDS with
+// consecutive lanes on consecutive columns (the system is row-major).
 template <typename T>
 __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__restrict__ S, T *__restrict__ sys) {
-    const int e = blockIdx.y;
+    const int e = blockIdx.z;
     const int *to = dm.toff + 7 * e;
     const int f = to[6], m = asm_pad(f);
-    const int64_t ld = e_ld(m, m);
+    const int ld = (int)e_ld(m, m);
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    if (r0 >= m || c0 >= ld) return;  // uniform per block
     T *base = sys + dm.asmsys_off[e];
-    const int64_t total = (int64_t)m * ld;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(t / ld), c = (int)(t % ld);
+    __shared__ double tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = r0 + tx, c = c0 + ty + 8 * q;
         double v = 0.0;
-        if (c < m) {
+        if (r < m && c < m) {
             if (r < f && c < f) {
                 int a = 0, b = 0;
                 while (r >= to[a + 1]) ++a;
@@ -137,10 +144,16 @@ __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__r
             } else {
                 v = (r == c) ? 1.0 : 0.0;
             }
-        } else if (c < 2 * m) {
+        } else if (r < m && c < 2 * m) {
             v = (c - m == r) ? 1.0 : 0.0;
         }
-        base[t] = (T)v;
+        tile[tx][ty + 8 * q] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = r0 + ty + 8 * q, c = c0 + tx;
+        if (r < m && c < ld) base[(int64_t)r * ld + c] = (T)tile[ty + 8 * q][tx];
     }
 }
 
@@ -338,7 +351,7 @@ __global__ void __launch_bounds__(256) k_combine(const double *__restrict__ V, i
 // per wave, then a shuffle reduction.  The back substitution goes by 64-row
 // blocks: the diagonal block by wave 0 in LDS, then the rows above update
 // with the block's solution.
-constexpr int kRB = 64, kRT = 1024, kRW = kRT / 64;
+constexpr int kRB = 64, kRT = 1024, kRW = kRT / 64, kRQ = 4;  // kRQ rows in flight per wave
 
 __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub, const double *__restrict__ Ebase,
                                                  const double *__restrict__ dUhat, double *__restrict__ dQU) {
@@ -362,17 +375,19 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
         return v;
     };
-    // y = Y_r + Y_B dUh, four rows per wave at a time
-    for (int i = 4 * wave; i < n; i += 4 * kRW) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // y = Y_r + Y_B dUh, kRQ rows per wave at a time
+    for (int i = kRQ * wave; i < n; i += kRQ * kRW) {
+        double acc[kRQ];
+#pragma unroll
+        for (int q = 0; q < kRQ; ++q) acc[q] = 0.0;
         for (int j = lane; j < f; j += 64) {
             const double dj = sd[j];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < kRQ; ++q)
                 if (i + q < n) acc[q] += E[(int64_t)(i + q) * ld + n + j] * dj;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kRQ; ++q) {
             const double v = wave_sum(acc[q]);
             if (lane == 0 && i + q < n) sy[i + q] = v + E[(int64_t)(i + q) * ld + n + f];
         }
@@ -399,13 +414,13 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
             __syncthreads();
             // rows above: y[r] -= U[r][i0:i1] x[i0:i1], lane c takes column i0 + c
             const double xl = (lane < nb) ? sy[i0 + lane] : 0.0;
-            for (int r = 4 * wave; r < i0; r += 4 * kRW) {
-                double v[4];
+            for (int r = kRQ * wave; r < i0; r += kRQ * kRW) {
+                double v[kRQ];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < kRQ; ++q)
                     v[q] = (r + q < i0 && lane < nb) ? E[(int64_t)(r + q) * ld + i0 + lane] * xl : 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < kRQ; ++q) {
                     const double t = wave_sum(v[q]);
                     if (lane == 0 && r + q < i0) sy[r + q] -= t;
                 }
@@ -451,10 +466,12 @@ int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, 
     size_t sys_bytes = (es * (size_t)ctx->asmsys_off[ctx->n_elem] + 255) / 256 * 256;
     void *iwork = (void *)((char *)work + sys_bytes);
     // FP64 inverses for FP64 storage; FP32 storage is inverted in FP32 (FP32 matrix cores)
+    const int mmax = asm_pad(ctx->max_f);
+    const dim3 bgrid((int)((e_ld(mmax, mmax) + 31) / 32), (mmax + 31) / 32, ctx->n_elem);
     if (prec == HDG_FP64)
-        hipLaunchKernelGGL(k_asm_build<double>, dim3(64, ctx->n_elem), dim3(256), 0, s, dm, S, (double *)sys);
+        hipLaunchKernelGGL(k_asm_build<double>, bgrid, dim3(256), 0, s, dm, S, (double *)sys);
     else
-        hipLaunchKernelGGL(k_asm_build<float>, dim3(64, ctx->n_elem), dim3(256), 0, s, dm, S, (float *)sys);
+        hipLaunchKernelGGL(k_asm_build<float>, bgrid, dim3(256), 0, s, dm, S, (float *)sys);
     int err = run_asm_inversion(ctx, prec, sys, info, iwork, s);
     if (err) return err;
     const int maxf = ctx->max_f;
