@@ -80,6 +80,7 @@ constexpr int kHalf = 32;     // the panel is factored as two halves (sub-panels
 constexpr int kPT = 512;      // panel kernel threads
 constexpr int kRPC = 32;      // columns per k_rowperm workgroup
 constexpr int kBC = 32;       // columns per k_blocku workgroup
+constexpr int kCR = 128;      // trace rows per k_crows workgroup
 static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptions");
 // A recorded permutation of w swaps (row base+jj <-> piv[jj]): [0] = number of
 // displaced rows, [1 .. W] source row of each top row, then (dst, src) pairs.
@@ -638,7 +639,9 @@ __global__ void __launch_bounds__(256) k_half(DevMesh dm, SysDesc sd, int e0, in
 }
 
 // Multipliers of the trace rows n..n+f-1 in the panel columns [kp, kp+nb):
-// L_C = C_panel U11^{-1} (matrix cores), one workgroup per 64 trace rows.
+// L_C = C_panel U11^{-1} (matrix cores), in place, one workgroup per 128 trace
+// rows: U11^{-1} in LDS, the C rows read from the cache as matrix-core operands,
+// each wave on its own 32 rows.
 template <int TAG, typename T>
 __global__ void __launch_bounds__(256) k_crows(DevMesh dm, SysDesc sd, int e0, int kp, int slot,
                                                T *__restrict__ Ebase, WS<T> ws) {
@@ -647,29 +650,36 @@ __global__ void __launch_bounds__(256) k_crows(DevMesh dm, SysDesc sd, int e0, i
     const ElemDims dd = elem_dims(dm, sd, e);
     if (kp >= dd.n) return;
     const int nb = min(kNB, dd.n - kp);
-    const int r0 = dd.n + blockIdx.x * 64;
-    if (r0 >= dd.mrows) return;
+    const int r0 = dd.n + blockIdx.x * kCR;
+    if (r0 >= dd.mrows) return;  // uniform per block
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ T sX[64][65];
+    const int kq = lane >> 4, cl = lane & 15;
     __shared__ T sU[kNB][kNB + 1];
     const T *ui = ws.d + (int64_t)blockIdx.y * ws.ds + (2 + slot) * kNB * kNB;
     for (int t = tid; t < kNB * kNB; t += 256) sU[t >> 6][t & 63] = ui[t];
-    for (int t = tid; t < 64 * 64; t += 256) {
-        const int r = t >> 6, c = t & 63;
-        sX[r][c] = (r0 + r < dd.mrows && c < nb) ? E[(int64_t)(r0 + r) * ld + kp + c] : T(0);
-    }
     __syncthreads();
-    acc_t acc[4];
-    mfma_64x64<T>(sX, sU, acc, lane, wave);
+    // K = nb rounded up to 16: U11^{-1} is zero beyond nb, and the C entries there
+    // are finite (the next panel's columns, or the row padding)
+    const int kend = (nb + 15) & ~15;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int h = 0; h < 2; ++h) {
+        const int rb = r0 + 32 * wave + 16 * h;
+        if (rb >= dd.mrows) break;  // uniform per wave; no barrier follows
+        acc_t acc[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = r0 + 16 * wave + MF<T>::rowof(lane, q), c = 16 * j + (lane & 15);
-            if (r < dd.mrows && c < nb) E[(int64_t)r * ld + kp + c] = acc[j][q];
-        }
+        for (int j = 0; j < 4; ++j) acc[j] = (acc_t){T(0), T(0), T(0), T(0)};
+        const int ra = min(rb + cl, dd.mrows - 1);
+        mfma_rowblock<T, 4>(E + (int64_t)ra * ld + kp + kq, sU, 0, 0, kend, kq, cl, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = rb + MF<T>::rowof(lane, q), c = 16 * j + cl;
+                if (r < dd.mrows && c < nb) E[(int64_t)r * ld + kp + c] = acc[j][q];
+            }
+    }
 }
 
 // ------------------------------------------------------- row permutation
@@ -1619,8 +1629,8 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
                                    kp, E);
             half(2);
             if (maxf_rows > 0)
-                hipLaunchKernelGGL((k_crows<TAG, T>), dim3((maxf_rows + 63) / 64, ne), dim3(256), 0, s, dm, sd, e0, kp,
-                                   slot, E, wb);
+                hipLaunchKernelGGL((k_crows<TAG, T>), dim3((maxf_rows + kCR - 1) / kCR, ne), dim3(256), 0, s, dm, sd, e0,
+                                   kp, slot, E, wb);
         };
         panel(k0, 0);
         if (maxn - k0 > kNB) {
