@@ -862,7 +862,6 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ T sX[kNBO][kBC + 1];
-    __shared__ T sU[MODE == 1 ? kNBO : 1][kBC + 1];
     __shared__ int sperm[kPerm128];
     const int *wi = ws.i + (int64_t)el * ws.is;
     const T *wd = ws.d + (int64_t)el * ws.ds;
@@ -877,7 +876,6 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
         const int t = tid + 256 * q;
         const int r = t / kBC, c = t % kBC;
         sX[r][c] = (r < nrows && c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : T(0);
-        if (MODE == 1) sU[r][c] = (c0 + c < c_end) ? E[(int64_t)(k0 - kNBO + r) * ld + c0 + c] : T(0);
     }
     // a top row's source may be a displaced row: its old content must be read
     // before the displaced copies overwrite it
@@ -908,8 +906,25 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
             acc_t a[kBC / 16];
 #pragma unroll
             for (int j = 0; j < kBC / 16; ++j) a[j] = (acc_t){T(0), T(0), T(0), T(0)};
+            // both operands from the cache: L_A rows (lane's row) and U12_A (lane's
+            // column, masked beyond the last column)
             const int r = min(k0 + 16 * rb + cl, dd.n - 1);
-            mfma_rowblock<T, kBC / 16>(E + (int64_t)r * ld + k0 - kNBO + kq, sU, 0, 0, kNBO, kq, cl, a);
+            const T *arow = E + (int64_t)r * ld + k0 - kNBO + kq;
+            const T *bcol = E + (int64_t)(k0 - kNBO + kq) * ld + c0 + cl;
+            for (int kb = 0; kb < kNBO; kb += 16) {
+                T av[4], bv[4][kBC / 16];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    av[q] = arow[kb + 4 * q];
+#pragma unroll
+                    for (int j = 0; j < kBC / 16; ++j)
+                        bv[q][j] = (c0 + 16 * j + cl < c_end) ? bcol[(int64_t)(kb + 4 * q) * ld + 16 * j] : T(0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int j = 0; j < kBC / 16; ++j) a[j] = MF<T>::mfma(av[q], bv[q][j], a[j]);
+            }
 #pragma unroll
             for (int j = 0; j < kBC / 16; ++j)
 #pragma unroll
