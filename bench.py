@@ -267,7 +267,7 @@ def main():
         "config": {"workload": wl.name, "elements": ne, "p": p,
                    "n_interior": n if len(degrees) == 1 else f"{min(ns)}-{max(ns)}",
                    "f_trace": f if len(degrees) == 1 else f"{min(fs)}-{max(fs)}",
-                   "chunk": chunk or ne, "gmres_iterations": st.m,
+                   "chunk": chunk or ne, "batches": [n for _, n in st.chunks], "gmres_iterations": st.m,
                    "schwarz": "element-block, " + ("FP32 inverses" if big else "FP64"), "precision": "FP64",
                    "step": f"residual+Jacobian, condensation, assembly, Schwarz set-up, GMRES({st.m}), recovery"},
         "graph_ms_per_step": graph_ms,

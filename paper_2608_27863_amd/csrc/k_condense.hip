@@ -178,6 +178,18 @@ __device__ void block_net_perm(int base, int w, const int *piv, int *top_src, in
     if (tid == 0) *ndisp = s_wcnt[0] + s_wcnt[1];
 }
 
+// XCD-aware work mapping: consecutive workgroups go round-robin over the 8 XCDs;
+// XCD x takes elements x, x+8, x+16, ... with all their tiles, so an element's
+// tiles share one L2 and every XCD gets an equal share of the element sizes
+// however the elements are ordered.  False past the last element.
+__device__ inline bool xcd_item(int ne, int tiles, int &el, int &t) {
+    const int xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+    el = 8 * (idx / tiles) + xcd;
+    t = idx % tiles;
+    return el < ne;
+}
+inline int xcd_grid(int ne, int tiles) { return 8 * ((ne + 7) / 8) * tiles; }
+
 // ------------------------------------------------------------------ panel
 // Factor the panel columns [k0, k0+nb) over the pivot rows [k0, n) (the trace
 // rows n.. get their multipliers from k_crows).  Rows are distributed over the
@@ -836,11 +848,8 @@ template <int MODE, int TAG, typename T>
 __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int rhs, int CB,
                                                 int CW, int tiles, T *__restrict__ Ebase, WS<T> ws) {
     typedef typename MF<T>::acc_t acc_t;
-    const int total = ne * tiles;
-    const int per_xcd = (total + 7) / 8;
-    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (w >= total) return;
-    const int el = w / tiles;
+    int el, tl;
+    if (!xcd_item(ne, tiles, el, tl)) return;
     const int e = e0 + el;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
@@ -856,7 +865,7 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
         c_begin = k0 + max(nrows, min(CB, rem));
         c_end = CW > 0 ? k0 + min(CW, rem) : dd.ncols;
     }
-    const int c0 = c_begin + (w % tiles) * kBC;
+    const int c0 = c_begin + tl * kBC;
     if (c0 >= c_end) return;  // uniform per block
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
@@ -1001,13 +1010,8 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     typedef UpdCfg<T> C;
     typedef typename MF<T>::v16 v16;
     typedef typename MF<T>::acc_t acc_t;
-    // XCD-aware mapping: consecutive workgroups go round-robin over the 8 XCDs;
-    // give each XCD a contiguous range of (element, tile) work items.
-    const int total = ne * tiles_m * tiles_n;
-    const int per_xcd = (total + 7) / 8;
-    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (w >= total) return;
-    const int el = w / (tiles_m * tiles_n), t = w % (tiles_m * tiles_n);
+    int el, t;
+    if (!xcd_item(ne, tiles_m * tiles_n, el, t)) return;
     const int e = e0 + el;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
@@ -1208,11 +1212,8 @@ __global__ void __launch_bounds__(256, 2) k_lbsolve(DevMesh dm, SysDesc sd, int 
     typedef UpdCfg<T> C;
     typedef typename MF<T>::v16 v16;
     typedef typename MF<T>::acc_t acc_t;
-    const int total = ne * tiles_n;
-    const int per_xcd = (total + 7) / 8;
-    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (w >= total) return;
-    const int el = w / tiles_n;
+    int el, tl;
+    if (!xcd_item(ne, tiles_n, el, tl)) return;
     const int e = e0 + el;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
@@ -1220,7 +1221,7 @@ __global__ void __launch_bounds__(256, 2) k_lbsolve(DevMesh dm, SysDesc sd, int 
     const int kb = k0 + nb;  // first row (and column) of the solved part
     const int K = dd.n - kb;
     const int r0 = k0, rend = kb;
-    const int c0 = dd.n + (w % tiles_n) * kTN, cend = dd.ncols;
+    const int c0 = dd.n + tl * kTN, cend = dd.ncols;
     if (c0 >= cend) return;  // uniform per block
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const T *wd = ws.d + (int64_t)el * ws.ds;
@@ -1455,11 +1456,8 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
     typedef UpdCfg<double> C;
     typedef MF<double>::v16 v16;
     typedef MF<double>::acc_t acc_t;
-    const int total = ne * tiles_m * tiles_n;
-    const int per_xcd = (total + 7) / 8;
-    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (w >= total) return;
-    const int el = w / (tiles_m * tiles_n), t = w % (tiles_m * tiles_n);
+    int el, t;
+    if (!xcd_item(ne, tiles_m * tiles_n, el, t)) return;
     const int e = e0 + el;
     int n, f;
     int64_t ld, ldx;
@@ -1619,14 +1617,13 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
     auto update = [&](int k0, int KW, int CB, int CW, int rows, int cols) {
         if (rows <= 0 || cols <= 0) return;
         const int tm = (rows + kTM - 1) / kTM, tn = (cols + kTN - 1) / kTN;
-        const int total = ne * tm * tn;
-        hipLaunchKernelGGL((k_update<T, TAG, kRangeLU>), dim3((total + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne,
+        hipLaunchKernelGGL((k_update<T, TAG, kRangeLU>), dim3(xcd_grid(ne, tm * tn)), dim3(256), 0, s, dm, sd, e0, ne,
                            k0, KW, CB, CW, tm, tn, E);
     };
     auto blocku = [&](auto mode, int k0, const WS<T> &wb, int CB, int CW, int cols) {
         if (cols <= 0) return;
         const int tiles = (cols + kBC - 1) / kBC;
-        hipLaunchKernelGGL((k_blocku<decltype(mode)::value, TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_blocku<decltype(mode)::value, TAG, T>), dim3(xcd_grid(ne, tiles)), dim3(256), 0, s,
                            dm, sd, e0, ne, k0, 0, CB, CW, tiles, E, wb);
     };
     // panels of the 128-column block at k0 and their records
@@ -1723,7 +1720,7 @@ static void run_back_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne
     const DevMesh &dm = ctx->dm;
     const int tn = (rhs_cols + kTN - 1) / kTN;
     for (int k0 = (maxn - 1) / kNBO * kNBO; k0 >= 0; k0 -= kNBO)
-        hipLaunchKernelGGL((k_lbsolve<T, TAG>), dim3((ne * tn + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, k0, tn, E,
+        hipLaunchKernelGGL((k_lbsolve<T, TAG>), dim3(xcd_grid(ne, tn)), dim3(256), 0, s, dm, sd, e0, ne, k0, tn, E,
                            block_ws(ws, k0));
 }
 
@@ -1736,15 +1733,15 @@ static void run_forward_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int
     const int tn = (rhs_cols + kTN - 1) / kTN;
     const int tiles = (rhs_cols + kBC - 1) / kBC;
     for (int K0 = 0; K0 < maxn; K0 += 2 * kNBO) {
-        hipLaunchKernelGGL((k_blocku<0, TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne, K0, 1,
+        hipLaunchKernelGGL((k_blocku<0, TAG, T>), dim3(xcd_grid(ne, tiles)), dim3(256), 0, s, dm, sd, e0, ne, K0, 1,
                            0, 0, tiles, E, block_ws(ws, K0));
         if (maxn - K0 > kNBO)
-            hipLaunchKernelGGL((k_blocku<1, TAG, T>), dim3((ne * tiles + 7) / 8 * 8), dim3(256), 0, s, dm, sd, e0, ne,
+            hipLaunchKernelGGL((k_blocku<1, TAG, T>), dim3(xcd_grid(ne, tiles)), dim3(256), 0, s, dm, sd, e0, ne,
                                K0 + kNBO, 1, 0, 0, tiles, E, block_ws(ws, K0 + kNBO));
         const int rows = maxn - K0 - 2 * kNBO;
         if (rows > 0) {
             const int tm = (rows + kTM - 1) / kTM;
-            hipLaunchKernelGGL((k_update<T, TAG, kRangeFwd>), dim3((ne * tm * tn + 7) / 8 * 8), dim3(256), 0, s, dm, sd,
+            hipLaunchKernelGGL((k_update<T, TAG, kRangeFwd>), dim3(xcd_grid(ne, tm * tn)), dim3(256), 0, s, dm, sd,
                                e0, ne, K0, 2 * kNBO, 0, 0, tm, tn, E);
         }
     }
@@ -1830,7 +1827,7 @@ int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double
     const int tm_r = (maxn + kTM - 1) / kTM;
     for (int it = 0; it < refine; ++it) {
         // R = [B | R_qu] - A X in FP64 (into the FP32 right-hand columns), d = A^{-1} R, X += d
-        hipLaunchKernelGGL(k_gemm64<0>, dim3((ne * tm_r * tn + 7) / 8 * 8), dim3(256), 0, s, dm, e0, ne, tm_r, tn,
+        hipLaunchKernelGGL(k_gemm64<0>, dim3(xcd_grid(ne, tm_r * tn)), dim3(256), 0, s, dm, e0, ne, tm_r, tn,
                            (const double *)E, (const double *)X, M, SK);
         forward_solve();
         back_solve();
@@ -1841,7 +1838,7 @@ int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double
     }
     // [S^K | -g^K] = [D | R_uh] - C X (FP64), stored as [S^K | g^K]
     const int tm_s = (maxf + kTM - 1) / kTM;
-    hipLaunchKernelGGL(k_gemm64<1>, dim3((ne * tm_s * tn + 7) / 8 * 8), dim3(256), 0, s, dm, e0, ne, tm_s, tn,
+    hipLaunchKernelGGL(k_gemm64<1>, dim3(xcd_grid(ne, tm_s * tn)), dim3(256), 0, s, dm, e0, ne, tm_s, tn,
                        (const double *)E, (const double *)X, M, SK);
     return (int)hipGetLastError();
 }

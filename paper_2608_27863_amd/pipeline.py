@@ -29,6 +29,16 @@ class NewtonStep:
         ne = c.n_elem
         self.chunk = ne if chunk is None else int(chunk)
         self.chunks = [(e0, min(self.chunk, ne - e0)) for e0 in range(0, ne, self.chunk)]
+        # size buckets: a mesh whose degrees form a few contiguous runs (elements
+        # numbered by degree) is split at the run boundaries, one size of
+        # element system per batch of launches
+        ep = np.asarray(wl.mesh.elem_p)
+        cuts = [0] + [int(i) + 1 for i in np.nonzero(ep[1:] != ep[:-1])[0]] + [ne]
+        if 2 < len(cuts) <= 5:
+            self.chunks = []
+            for lo, hi in zip(cuts[:-1], cuts[1:]):
+                for a in range(lo, hi, self.chunk):
+                    self.chunks.append((a, min(self.chunk, hi - a)))
         f64 = dict(dtype=torch.float64, device=device)
 
         def buf(name, numel, dtype=torch.float64, zero=False):

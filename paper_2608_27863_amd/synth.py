@@ -203,6 +203,24 @@ def box_mesh(n: tuple, lengths=(2 * math.pi,) * 3, periodic=(True, True, True),
 
 
 # ---------------------------------------------------------------- positions
+def group_by_degree(mesh: Mesh) -> Mesh:
+    """The same mesh with its elements renumbered by degree (stable): every
+    degree is one contiguous range of elements, so that a batch of one degree
+    (one size of element system) can be condensed by launches of its own."""
+    perm = np.argsort(mesh.elem_p, kind="stable")
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    fe = mesh.face_elem.copy()
+    for side in range(2):
+        e = fe[:, side, 0]
+        ok = e >= 0
+        e[ok] = inv[e[ok]]
+        fe[:, side, 0] = e
+    return dataclasses.replace(mesh, elem_vert=np.ascontiguousarray(mesh.elem_vert[perm]),
+                               elem_face=np.ascontiguousarray(mesh.elem_face[perm]),
+                               face_elem=fe, elem_p=np.ascontiguousarray(mesh.elem_p[perm]))
+
+
 def _trilinear(X8: np.ndarray, xi: np.ndarray) -> np.ndarray:
     """Map reference points xi [..., 3] in [-1,1]^3 with vertex coords X8 [8, 3]."""
     out = np.zeros(xi.shape[:-1] + (3,))
@@ -357,7 +375,8 @@ def config(idx: int, *, n_override: Optional[int] = None) -> Workload:
     0: 4^3 periodic TGV, p=2, M=0.1, noise 1e-3.
     1: 8^3 periodic supersonic TGV, p=3, M=1.25, smooth AV field in [0, 1e-3].
     2: same inputs as 1 (the mixed-precision run).
-    3: 20x10x10 wall-stretched perturbed box, p drawn from {2,3,4}, M=0.5.
+    3: 20x10x10 wall-stretched perturbed box, p drawn from {2,3,4}, M=0.5,
+       elements numbered by degree (one contiguous range per degree).
     4: 12^3 periodic supersonic TGV, p=4, noise 1e-3.
     ``n_override`` shrinks the cube for quick tests (periodic configs only).
     """
@@ -379,8 +398,8 @@ def config(idx: int, *, n_override: Optional[int] = None) -> Workload:
         ly = float(yc[-1])
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([3, 7])))
         pe = rng.choice([2, 3, 4], size=nx * ny * nz, p=[0.3, 0.5, 0.2])
-        mesh = box_mesh((nx, ny, nz), lengths=(lx, ly, lz), periodic=(True, False, True),
-                        y_coords=yc, perturb=0.02, p=pe, seed=3)
+        mesh = group_by_degree(box_mesh((nx, ny, nz), lengths=(lx, ly, lz), periodic=(True, False, True),
+                                        y_coords=yc, perturb=0.02, p=pe, seed=3))
         f = lambda x: bl_state(x, 0.5, ly)
         return make_state(mesh, f, mach=0.5, noise=1e-3, seed=3, name="bl20x10x10-p234-M0.5",
                           gmres_m=30, boundary_field=f)
