@@ -1052,29 +1052,33 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     }
     const int bcol = c0 + bc;
     const int bcolc = min(bcol, (cend - 1) & ~(C::V - 1));
+    // The raw loads stay in registers while the current chunk's products run; the
+    // out-of-range entries are zeroed only when the chunk is stored to LDS, so no
+    // wait on the loads precedes the matrix-core work.
     auto load_chunk = [&](int kc, v16 *ra, v16 *rb) {
-        const int gk = kc + ak;
-        const int gkc = min(gk, (K - 1) & ~(C::V - 1));
+        const int gkc = min(kc + ak, (K - 1) & ~(C::V - 1));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const v16 v = *(const v16 *)(arow[q] + gkc);
-#pragma unroll
-            for (int i = 0; i < C::V; ++i) ra[q][i] = (aok[q] && gk + i < K) ? v[i] : T(0);
-        }
+        for (int q = 0; q < 4; ++q) ra[q] = *(const v16 *)(arow[q] + gkc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gk2 = kc + C::KPQ * q + bk;
-            const bool k2ok = gk2 < K;
-            const v16 v = *(const v16 *)(E + (int64_t)(k0 + min(gk2, K - 1)) * ld + bcolc);
-#pragma unroll
-            for (int i = 0; i < C::V; ++i) rb[q][i] = (k2ok && bcol + i < cend) ? v[i] : T(0);
+            rb[q] = *(const v16 *)(E + (int64_t)(k0 + min(gk2, K - 1)) * ld + bcolc);
         }
     };
-    auto store_chunk = [&](int buf, const v16 *ra, const v16 *rb) {
+    auto store_chunk = [&](int buf, int kc, const v16 *ra, const v16 *rb) {
+        const int gk = kc + ak;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            *(v16 *)&sA[buf][32 * q + ar][ak] = (sizeof(T) == 8) ? -ra[q] : ra[q];
-            *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = rb[q];
+            v16 a, b;
+            const int gk2 = kc + C::KPQ * q + bk;
+            const bool k2ok = gk2 < K;
+#pragma unroll
+            for (int i = 0; i < C::V; ++i) {
+                a[i] = (aok[q] && gk + i < K) ? ra[q][i] : T(0);
+                b[i] = (k2ok && bcol + i < cend) ? rb[q][i] : T(0);
+            }
+            *(v16 *)&sA[buf][32 * q + ar][ak] = (sizeof(T) == 8) ? -a : a;
+            *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = b;
         }
     };
     // C is read at the start so that its loads overlap the operand loads.  FP64:
@@ -1106,7 +1110,7 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
         }
     v16 ra[4], rb[4];
     load_chunk(0, ra, rb);
-    store_chunk(0, ra, rb);
+    store_chunk(0, 0, ra, rb);
     __syncthreads();
     const int nchunks = (K + C::KC - 1) / C::KC;
     for (int ch = 0; ch < nchunks; ++ch) {
@@ -1138,7 +1142,7 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
             }
         }
         if (ch + 1 < nchunks) {
-            store_chunk(buf ^ 1, ra, rb);
+            store_chunk(buf ^ 1, (ch + 1) * C::KC, ra, rb);
             __syncthreads();
         }
     }
@@ -1273,34 +1277,36 @@ __global__ void __launch_bounds__(256, 2) k_lbsolve(DevMesh dm, SysDesc sd, int 
         }
         const int bcol = c0 + bc;
         const int bcolc = min(bcol, (cend - 1) & ~(C::V - 1));
+        // raw loads in registers; out-of-range entries zeroed at the LDS store
         auto load_chunk = [&](int kc, v16 *ra, v16 *rb) {
-            const int gk = kc + ak;
-            const int gkc = min(gk, (K - 1) & ~(C::V - 1));
+            const int gkc = min(kc + ak, (K - 1) & ~(C::V - 1));
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const v16 v = *(const v16 *)(arow[q] + gkc);
-#pragma unroll
-                for (int i = 0; i < C::V; ++i) ra[q][i] = (aok[q] && gk + i < K) ? v[i] : T(0);
-            }
+            for (int q = 0; q < 4; ++q) ra[q] = *(const v16 *)(arow[q] + gkc);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gk2 = kc + C::KPQ * q + bk;
-                const bool k2ok = gk2 < K;
-                const v16 v = *(const v16 *)(E + (int64_t)(kb + min(gk2, K - 1)) * ld + bcolc);
-#pragma unroll
-                for (int i = 0; i < C::V; ++i) rb[q][i] = (k2ok && bcol + i < cend) ? v[i] : T(0);
+                rb[q] = *(const v16 *)(E + (int64_t)(kb + min(gk2, K - 1)) * ld + bcolc);
             }
         };
-        auto store_chunk = [&](int buf, const v16 *ra, const v16 *rb) {
+        auto store_chunk = [&](int buf, int kc, const v16 *ra, const v16 *rb) {
+            const int gk = kc + ak;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                *(v16 *)&sA[buf][32 * q + ar][ak] = kOntoC ? -ra[q] : ra[q];
-                *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = rb[q];
+                v16 a, b;
+                const int gk2 = kc + C::KPQ * q + bk;
+                const bool k2ok = gk2 < K;
+#pragma unroll
+                for (int i = 0; i < C::V; ++i) {
+                    a[i] = (aok[q] && gk + i < K) ? ra[q][i] : T(0);
+                    b[i] = (k2ok && bcol + i < cend) ? rb[q][i] : T(0);
+                }
+                *(v16 *)&sA[buf][32 * q + ar][ak] = kOntoC ? -a : a;
+                *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = b;
             }
         };
         v16 ra[4], rb[4];
         load_chunk(0, ra, rb);
-        store_chunk(0, ra, rb);
+        store_chunk(0, 0, ra, rb);
         __syncthreads();
         const int nchunks = (K + C::KC - 1) / C::KC;
         for (int ch = 0; ch < nchunks; ++ch) {
@@ -1331,7 +1337,7 @@ __global__ void __launch_bounds__(256, 2) k_lbsolve(DevMesh dm, SysDesc sd, int 
                 }
             }
             if (ch + 1 < nchunks) {
-                store_chunk(buf ^ 1, ra, rb);
+                store_chunk(buf ^ 1, (ch + 1) * C::KC, ra, rb);
                 __syncthreads();
             }
         }
@@ -1484,29 +1490,30 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
     }
     const int bcol = c0 + bc;
     const int bcolc = min(bcol, (N - 1) & ~1);
+    // raw loads in registers; out-of-range entries zeroed at the LDS store
     auto load_chunk = [&](int kc, v16 *ra, v16 *rb) {
-        const int gk = kc + ak;
-        const int gkc = min(gk, (K - 1) & ~1);
+        const int gkc = min(kc + ak, (K - 1) & ~1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const v16 v = *(const v16 *)(arow[q] + gkc);
-            ra[q].x = (aok[q] && gk < K) ? v.x : 0.0;
-            ra[q].y = (aok[q] && gk + 1 < K) ? v.y : 0.0;
-        }
+        for (int q = 0; q < 4; ++q) ra[q] = *(const v16 *)(arow[q] + gkc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gk2 = kc + C::KPQ * q + bk;
-            const bool k2ok = gk2 < K;
-            const v16 v = *(const v16 *)(X + (int64_t)min(gk2, K - 1) * ldx + bcolc);
-            rb[q].x = (k2ok && bcol < N) ? v.x : 0.0;
-            rb[q].y = (k2ok && bcol + 1 < N) ? v.y : 0.0;
+            rb[q] = *(const v16 *)(X + (int64_t)min(gk2, K - 1) * ldx + bcolc);
         }
     };
-    auto store_chunk = [&](int buf, const v16 *ra, const v16 *rb) {
+    auto store_chunk = [&](int buf, int kc, const v16 *ra, const v16 *rb) {
+        const int gk = kc + ak;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            *(v16 *)&sA[buf][32 * q + ar][ak] = ra[q];
-            *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = rb[q];
+            v16 a, b;
+            const int gk2 = kc + C::KPQ * q + bk;
+            const bool k2ok = gk2 < K;
+            a.x = (aok[q] && gk < K) ? ra[q].x : 0.0;
+            a.y = (aok[q] && gk + 1 < K) ? ra[q].y : 0.0;
+            b.x = (k2ok && bcol < N) ? rb[q].x : 0.0;
+            b.y = (k2ok && bcol + 1 < N) ? rb[q].y : 0.0;
+            *(v16 *)&sA[buf][32 * q + ar][ak] = a;
+            *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = b;
         }
     };
     // K chunks this tile needs
@@ -1538,7 +1545,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
     int buf = 0;
     if (ch < nchunks) {
         load_chunk(ch * C::KC, ra, rb);
-        store_chunk(0, ra, rb);
+        store_chunk(0, ch * C::KC, ra, rb);
         __syncthreads();
     }
     while (ch < nchunks) {
@@ -1557,7 +1564,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
                 for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<double>::mfma(av[bi], bv[bj], acc[bi][bj]);
         }
         if (nx < nchunks) {
-            store_chunk(buf ^ 1, ra, rb);
+            store_chunk(buf ^ 1, nx * C::KC, ra, rb);
             __syncthreads();
         }
         buf ^= 1;
