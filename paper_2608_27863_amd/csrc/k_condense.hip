@@ -200,7 +200,7 @@ inline int xcd_grid(int ne, int tiles) { return 8 * ((ne + 7) / 8) * tiles; }
 // k_half (matrix cores, many workgroups) between the launches, which reads and
 // writes the panel's right part far fewer times.
 template <int R, int TAG, typename T>
-__global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase, int part,
+__global__ void __launch_bounds__(kPT, sizeof(T) == 4 ? 4 : 2) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase, int part,
                                                T *__restrict__ Ebase, WS<T> ws, int *__restrict__ info) {
     typedef typename MF<T>::v2 v2;
     const int e = e0 + blockIdx.x;
@@ -399,7 +399,13 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
                 }
             }
             __syncthreads();
-            // pivot rows below the sub-panel: E[r][right] -= L[r][0:w] U[0:w][right]
+            // pivot rows below the sub-panel: E[r][right] -= L[r][0:w] U[0:w][right].
+            // Each thread walks its own rows, so every access of a wave touches 64
+            // rows: 16-byte accesses halve (FP64) or quarter (FP32) their number.
+            // Aligned: nrloc > 0 only for w = kW, cb is a multiple of kW, ld of 8,
+            // and nrloc of 4, so no 16-byte group straddles the end of the range.
+            constexpr int VN = 16 / sizeof(T);
+            typedef T vq __attribute__((ext_vector_type(VN)));
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = cb + tid + kPT * i;
@@ -408,14 +414,25 @@ __global__ void __launch_bounds__(kPT) k_panel(DevMesh dm, SysDesc sd, int e0, i
                 for (int c8 = 0; c8 < nrloc; c8 += 8) {
                     T v[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = (c8 + q < nrloc) ? row[c8 + q] : T(0);
+                    for (int h = 0; h < 8; h += VN) {
+                        vq x = (vq)T(0);
+                        if (c8 + h < nrloc) x = *(const vq *)(row + c8 + h);
+#pragma unroll
+                        for (int u = 0; u < VN; ++u) v[h + u] = x[u];
+                    }
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
 #pragma unroll
                         for (int q = 0; q < 8; ++q) v[q] -= a[i][jj] * s_U[jj][(c8 + q) & (kNB - 1)];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (c8 + q < nrloc) row[c8 + q] = v[q];
+                    for (int h = 0; h < 8; h += VN) {
+                        if (c8 + h < nrloc) {
+                            vq x;
+#pragma unroll
+                            for (int u = 0; u < VN; ++u) x[u] = v[h + u];
+                            *(vq *)(row + c8 + h) = x;
+                        }
+                    }
                 }
             }
             __syncthreads();
