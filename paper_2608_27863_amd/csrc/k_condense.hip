@@ -202,7 +202,8 @@ inline int xcd_grid(int ne, int tiles) { return 8 * ((ne + 7) / 8) * tiles; }
 template <int R, int TAG, typename T>
 __global__ void __launch_bounds__(kPT, sizeof(T) == 4 ? 4 : 2) k_panel(DevMesh dm, SysDesc sd, int e0, int k0, int slot, int kbase, int part,
                                                T *__restrict__ Ebase, WS<T> ws, int *__restrict__ info) {
-    typedef typename MF<T>::v2 v2;
+    constexpr int kVN = 16 / sizeof(T);  // values per 16-byte access
+    typedef T vq __attribute__((ext_vector_type(kVN)));
     const int e = e0 + blockIdx.x;
     const ElemDims dd = elem_dims(dm, sd, e);
     if (k0 >= dd.n) return;
@@ -240,11 +241,12 @@ __global__ void __launch_bounds__(kPT, sizeof(T) == 4 ? 4 : 2) k_panel(DevMesh d
             const int r = cb + tid + kPT * i;
             const T *src = E + (int64_t)min(r, n - 1) * ld + cb;
             if (w == kW) {
+                // 16-byte loads (cb is a multiple of kW, ld of 8)
 #pragma unroll
-                for (int c = 0; c < kW; c += 2) {
-                    const v2 v = *(const v2 *)(src + c);
-                    a[i][c] = (r < n) ? v.x : T(0);
-                    a[i][c + 1] = (r < n) ? v.y : T(0);
+                for (int c = 0; c < kW; c += kVN) {
+                    const vq v = *(const vq *)(src + c);
+#pragma unroll
+                    for (int u = 0; u < kVN; ++u) a[i][c + u] = (r < n) ? v[u] : T(0);
                 }
             } else {
 #pragma unroll
@@ -334,7 +336,12 @@ __global__ void __launch_bounds__(kPT, sizeof(T) == 4 ? 4 : 2) k_panel(DevMesh d
             T *dst = E + (int64_t)r * ld + cb;
             if (r < n && w == kW) {
 #pragma unroll
-                for (int c = 0; c < kW; c += 2) *(v2 *)(dst + c) = (v2){a[i][c], a[i][c + 1]};
+                for (int c = 0; c < kW; c += kVN) {
+                    vq v;
+#pragma unroll
+                    for (int u = 0; u < kVN; ++u) v[u] = a[i][c + u];
+                    *(vq *)(dst + c) = v;
+                }
             } else if (r < n) {
 #pragma unroll
                 for (int c = 0; c < kW; ++c)
@@ -404,8 +411,6 @@ __global__ void __launch_bounds__(kPT, sizeof(T) == 4 ? 4 : 2) k_panel(DevMesh d
             // rows: 16-byte accesses halve (FP64) or quarter (FP32) their number.
             // Aligned: nrloc > 0 only for w = kW, cb is a multiple of kW, ld of 8,
             // and nrloc of 4, so no 16-byte group straddles the end of the range.
-            constexpr int VN = 16 / sizeof(T);
-            typedef T vq __attribute__((ext_vector_type(VN)));
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = cb + tid + kPT * i;
@@ -414,22 +419,22 @@ __global__ void __launch_bounds__(kPT, sizeof(T) == 4 ? 4 : 2) k_panel(DevMesh d
                 for (int c8 = 0; c8 < nrloc; c8 += 8) {
                     T v[8];
 #pragma unroll
-                    for (int h = 0; h < 8; h += VN) {
+                    for (int h = 0; h < 8; h += kVN) {
                         vq x = (vq)T(0);
                         if (c8 + h < nrloc) x = *(const vq *)(row + c8 + h);
 #pragma unroll
-                        for (int u = 0; u < VN; ++u) v[h + u] = x[u];
+                        for (int u = 0; u < kVN; ++u) v[h + u] = x[u];
                     }
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
 #pragma unroll
                         for (int q = 0; q < 8; ++q) v[q] -= a[i][jj] * s_U[jj][(c8 + q) & (kNB - 1)];
 #pragma unroll
-                    for (int h = 0; h < 8; h += VN) {
+                    for (int h = 0; h < 8; h += kVN) {
                         if (c8 + h < nrloc) {
                             vq x;
 #pragma unroll
-                            for (int u = 0; u < VN; ++u) x[u] = v[h + u];
+                            for (int u = 0; u < kVN; ++u) x[u] = v[h + u];
                             *(vq *)(row + c8 + h) = x;
                         }
                     }
