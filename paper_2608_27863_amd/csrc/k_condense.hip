@@ -133,7 +133,33 @@ __device__ inline ElemDims elem_dims(const DevMesh &dm, const SysDesc &sd, int e
 }
 
 template <typename T> __device__ inline void argmax_combine(T &v, int &r, T v2, int r2) {
-    if (v2 > v || (v2 == v && r2 < r)) { v = v2; r = r2; }
+    const bool take = (v2 > v) | ((v2 == v) & (r2 < r));  // selects, no branches
+    v = take ? v2 : v;
+    r = take ? r2 : r;
+}
+
+// Lane exchange by a DPP pattern (a VALU operand modifier, no LDS round trip).
+template <int CTRL> __device__ inline int dpp_int(int x) { return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false); }
+template <int CTRL> __device__ inline float dpp_val(float x) { return __int_as_float(dpp_int<CTRL>(__float_as_int(x))); }
+template <int CTRL> __device__ inline double dpp_val(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_int<CTRL>((int)b), hi = dpp_int<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, typename T> __device__ inline void argmax_dpp(T &v, int &r) {
+    argmax_combine(v, r, dpp_val<CTRL>(v), dpp_int<CTRL>(r));
+}
+// Wave-wide argmax (largest value, smallest row on ties), the result in every
+// lane.  The combine is associative and commutative, so the order of the steps
+// does not change the result: quad permutations [1,0,3,2] and [2,3,0,1] and
+// rotations by 4 and 8 inside each 16-lane row, then two lane exchanges across
+// rows.
+template <typename T> __device__ inline void wave_argmax(T &v, int &r) {
+    argmax_dpp<0xB1>(v, r);   // quad_perm [1,0,3,2]
+    argmax_dpp<0x4E>(v, r);   // quad_perm [2,3,0,1]
+    argmax_dpp<0x124>(v, r);  // row_ror 4
+    argmax_dpp<0x128>(v, r);  // row_ror 8
+    for (int off = 16; off < 64; off <<= 1) argmax_combine(v, r, __shfl_xor(v, off), __shfl_xor(r, off));
 }
 
 // Net row permutation of the swaps (row base+t <-> row piv[t]), t = 0 .. w-1, applied
@@ -269,11 +295,7 @@ __global__ void __launch_bounds__(kPT, sizeof(T) == 4 ? 4 : 2) k_panel(DevMesh d
                     argmax_combine(best, brow, v, r);
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const T v2_ = __shfl_xor(best, off);
-                const int r2 = __shfl_xor(brow, off);
-                argmax_combine(best, brow, v2_, r2);
-            }
+            wave_argmax(best, brow);
             if (lane == 0) { s_val[wave] = best; s_row[wave] = brow; }
             __syncthreads();
             T bv = s_val[0];
