@@ -149,17 +149,45 @@ template <int CTRL> __device__ inline double dpp_val(double x) {
 template <int CTRL, typename T> __device__ inline void argmax_dpp(T &v, int &r) {
     argmax_combine(v, r, dpp_val<CTRL>(v), dpp_int<CTRL>(r));
 }
+// Lane pairs (l, l ^ 16) or (l, l ^ 32) by the gfx950 row swaps: with both
+// operands the same register, the two results hold, lane by lane, the lane's own
+// value and its partner's (in some order), which is all a symmetric combine needs.
+template <int W> __device__ inline void swap_pair(unsigned x, unsigned &a, unsigned &b) {
+    const auto p = (W == 16) ? __builtin_amdgcn_permlane16_swap(x, x, false, false)
+                             : __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    a = p[0];
+    b = p[1];
+}
+template <int W> __device__ inline void argmax_swap(float &v, int &r) {
+    unsigned va, vb, ra, rb;
+    swap_pair<W>(__float_as_uint(v), va, vb);
+    swap_pair<W>((unsigned)r, ra, rb);
+    v = __uint_as_float(va);
+    r = (int)ra;
+    argmax_combine(v, r, __uint_as_float(vb), (int)rb);
+}
+template <int W> __device__ inline void argmax_swap(double &v, int &r) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    unsigned la, lb, ha, hb, ra, rb;
+    swap_pair<W>((unsigned)b, la, lb);
+    swap_pair<W>((unsigned)(b >> 32), ha, hb);
+    swap_pair<W>((unsigned)r, ra, rb);
+    v = __longlong_as_double((long long)(((unsigned long long)ha << 32) | la));
+    r = (int)ra;
+    argmax_combine(v, r, __longlong_as_double((long long)(((unsigned long long)hb << 32) | lb)), (int)rb);
+}
 // Wave-wide argmax (largest value, smallest row on ties), the result in every
 // lane.  The combine is associative and commutative, so the order of the steps
 // does not change the result: quad permutations [1,0,3,2] and [2,3,0,1] and
-// rotations by 4 and 8 inside each 16-lane row, then two lane exchanges across
-// rows.
+// rotations by 4 and 8 inside each 16-lane row, then the row swaps across 16 and
+// 32 lanes.  No step goes through LDS.
 template <typename T> __device__ inline void wave_argmax(T &v, int &r) {
     argmax_dpp<0xB1>(v, r);   // quad_perm [1,0,3,2]
     argmax_dpp<0x4E>(v, r);   // quad_perm [2,3,0,1]
     argmax_dpp<0x124>(v, r);  // row_ror 4
     argmax_dpp<0x128>(v, r);  // row_ror 8
-    for (int off = 16; off < 64; off <<= 1) argmax_combine(v, r, __shfl_xor(v, off), __shfl_xor(r, off));
+    argmax_swap<16>(v, r);
+    argmax_swap<32>(v, r);
 }
 
 // Net row permutation of the swaps (row base+t <-> row piv[t]), t = 0 .. w-1, applied
