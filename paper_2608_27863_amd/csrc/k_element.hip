@@ -349,9 +349,9 @@ __device__ inline void load_face_tables(const DevMesh &dm, int e, int p, int Nq,
     }
 }
 
-// Interior rows of one row field r of the element system, one workgroup per
-// (field, element): the 20 column blocks of A, the trace columns B, the residual
-// column and the padding, all written.  Gradient rows r = 3c+j hold the mass
+// Interior rows of one row field r of the element system (the workgroups that
+// share it are described below the helpers): the 20 column blocks of A, the
+// trace columns B, the residual column and the padding, all written.  Gradient rows r = 3c+j hold the mass
 // block (column field r) and K_j = int phi_k d_j phi_i (column field 15+c) and
 // zeros elsewhere; conservation rows r = 15+c hold the blocks of the point
 // Jacobians plus their face terms.
@@ -368,10 +368,18 @@ constexpr int kP1 = kMaxP + 1, kNQ = kMaxP + 2;
 
 // Instantiated per degree PT (LDS sized for it, loop bounds and index arithmetic
 // known at compile time); workgroups of elements of another degree return.
+// Row fields 0..14 (q) take one workgroup each; each of the five u row fields,
+// whose 20 column-field blocks all carry volume and face terms, is split over
+// kUG workgroups by column fields (the first of them also writes the trace
+// columns, the residual column and the padding).  The launch has 15 + 5 kUG
+// workgroups per element.
+constexpr int kUG = 4;
 template <int PT>
 __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
                                                              double *__restrict__ Ebase) {
-    const int r = blockIdx.x, e = e0 + blockIdx.y;
+    const int bx = blockIdx.x, e = e0 + blockIdx.y;
+    const int r = bx < 15 ? bx : 15 + (bx - 15) / kUG;  // row field
+    const int ug = bx < 15 ? 0 : (bx - 15) % kUG;        // column-field group of a u row
     if (dm.elem_p[e] != PT) return;
     constexpr int p = PT, p1 = p + 1, Np = p1 * p1 * p1, nq = p + 2, Nq = nq * nq * nq;
     // face-term blocks (6 p1^4) and trace-column blocks (5 p1^2 Nfp, face degree up to kMaxP)
@@ -485,7 +493,7 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
             for (int col = tid; col < n; col += blockDim.x)
                 if ((col < z0 || col >= z0 + Np) && (col < z1 || col >= z1 + Np)) Er[(int64_t)i * ld + col] = 0.0;
     } else {
-        for (int sblk = 0; sblk < 20; ++sblk) {
+        for (int sblk = ug * 20 / kUG; sblk < (ug + 1) * 20 / kUG; ++sblk) {
             const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
             __syncthreads();
             for (int t = tid; t < 4 * Nq; t += blockDim.x)
@@ -516,6 +524,7 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
             volume_block(sblk, true);
         }
     }
+    if (ug != 0) return;  // uniform per workgroup
     // ---- trace columns B: face by face, B_lf[cp][a0 a1][b0 b1] = sum_s c_cp(s) phi_a(s) mu_b(s)
     for (int lf = 0; lf < 6; ++lf) {
         const int pf1 = sPf[lf] + 1, nqf1 = sPf[lf] + 2, Nqf = sNqf[lf], Nfp = pf1 * pf1;
@@ -714,10 +723,10 @@ int launch_element_system(const hdg_ctx *ctx, int e0, int ne, const double *Q, c
     const double *qpc = qp;
     unsigned degrees = 0;
     for (int e = e0; e < e0 + ne; ++e) degrees |= 1u << ctx->elem_p[e];
-    if (degrees & 2u) hipLaunchKernelGGL(k_assemble_field_rows<1>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
-    if (degrees & 4u) hipLaunchKernelGGL(k_assemble_field_rows<2>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
-    if (degrees & 8u) hipLaunchKernelGGL(k_assemble_field_rows<3>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
-    if (degrees & 16u) hipLaunchKernelGGL(k_assemble_field_rows<4>, dim3(20, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    if (degrees & 2u) hipLaunchKernelGGL(k_assemble_field_rows<1>, dim3(15 + 5 * kUG, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    if (degrees & 4u) hipLaunchKernelGGL(k_assemble_field_rows<2>, dim3(15 + 5 * kUG, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    if (degrees & 8u) hipLaunchKernelGGL(k_assemble_field_rows<3>, dim3(15 + 5 * kUG, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
+    if (degrees & 16u) hipLaunchKernelGGL(k_assemble_field_rows<4>, dim3(15 + 5 * kUG, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
     hipLaunchKernelGGL(k_assemble_trace_rows, dim3(6, ne), dim3(256), 0, s, dm, P, e0, qpc, E);
     return (int)hipGetLastError();
 }
