@@ -1185,20 +1185,26 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     store_chunk(0, 0, ra, rb);
     __syncthreads();
     const int nchunks = (K + C::KC - 1) / C::KC;
+    // a wave whose 64 x 64 sub-tile lies wholly outside the range (the other half
+    // of a 64-column update, the rows past the end) only loads and synchronises,
+    // leaving its SIMD's matrix core to the waves of the other workgroup
+    const bool live = (r0 + wr < rend) && (c0 + wc < cend);  // uniform per wave
     for (int ch = 0; ch < nchunks; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nchunks) load_chunk((ch + 1) * C::KC, ra, rb);
+        if (live) {
 #pragma unroll
-        for (int kk = 0; kk < C::KC; kk += 4) {
-            T av[4], bv[4];
+            for (int kk = 0; kk < C::KC; kk += 4) {
+                T av[4], bv[4];
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][wr + 16 * bi + (lane & 15)][kk + (lane >> 4)];
+                for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][wr + 16 * bi + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][kk + (lane >> 4)][wc + 16 * bj + (lane & 15)];
+                for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][kk + (lane >> 4)][wc + 16 * bj + (lane & 15)];
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
+                for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<T>::mfma(av[bi], bv[bj], acc[bi][bj]);
+                    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<T>::mfma(av[bi], bv[bj], acc[bi][bj]);
+            }
         }
         if constexpr (!kOntoC) {
             // FP32: fold the partial product into C every kFold values of K, so the
