@@ -951,12 +951,23 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
     const int permoff = two ? kWsPerm128 : kWsPerm0;
     for (int t = tid; t < 1 + 3 * W; t += 256) sperm[t] = wi[permoff + t];
     __syncthreads();
-    // gather the permuted top rows (rows >= nrows are zero)
+    // gather the permuted top rows (rows >= nrows are zero): all loads in flight
+    // from clamped in-range addresses, the out-of-range entries zeroed at the store
+    {
+        constexpr int kG = kNBO * kBC / 256;
+        T g[kG];
 #pragma unroll
-    for (int q = 0; q < kNBO * kBC / 256; ++q) {
-        const int t = tid + 256 * q;
-        const int r = t / kBC, c = t % kBC;
-        sX[r][c] = (r < nrows && c0 + c < c_end) ? E[(int64_t)sperm[1 + r] * ld + c0 + c] : T(0);
+        for (int q = 0; q < kG; ++q) {
+            const int t = tid + 256 * q;
+            const int r = t / kBC, c = t % kBC;
+            g[q] = E[(int64_t)sperm[1 + min(r, nrows - 1)] * ld + min(c0 + c, c_end - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < kG; ++q) {
+            const int t = tid + 256 * q;
+            const int r = t / kBC, c = t % kBC;
+            sX[r][c] = (r < nrows && c0 + c < c_end) ? g[q] : T(0);
+        }
     }
     // a top row's source may be a displaced row: its old content must be read
     // before the displaced copies overwrite it
@@ -967,9 +978,9 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
     for (int t0 = tid; t0 < nd * kBC; t0 += 4 * 256) {
         T v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int t = t0 + 256 * q, d = t / kBC, c = t % kBC;
-            if (t < nd * kBC && c0 + c < c_end) v[q] = E[(int64_t)sperm[1 + W + 2 * d + 1] * ld + c0 + c];
+        for (int q = 0; q < 4; ++q) {  // clamped in-range reads, all in flight
+            const int t = t0 + 256 * q, d = min(t / kBC, nd - 1), c = t % kBC;
+            v[q] = E[(int64_t)sperm[1 + W + 2 * d + 1] * ld + min(c0 + c, c_end - 1)];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -988,23 +999,38 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
 #pragma unroll
             for (int j = 0; j < kBC / 16; ++j) a[j] = (acc_t){T(0), T(0), T(0), T(0)};
             // both operands from the cache: L_A rows (lane's row) and U12_A (lane's
-            // column, masked beyond the last column)
+            // column; columns past the last one are read at the last column and
+            // zeroed before use).  The next 16-wide step's operands are loaded
+            // while the current step's products run.
             const int r = min(k0 + 16 * rb + cl, dd.n - 1);
             const T *arow = E + (int64_t)r * ld + k0 - kNBO + kq;
-            const T *bcol = E + (int64_t)(k0 - kNBO + kq) * ld + c0 + cl;
-            for (int kb = 0; kb < kNBO; kb += 16) {
-                T av[4], bv[4][kBC / 16];
+            const T *bcol[kBC / 16];
+            bool cok[kBC / 16];
+#pragma unroll
+            for (int j = 0; j < kBC / 16; ++j) {
+                const int col = c0 + 16 * j + cl;
+                cok[j] = col < c_end;
+                bcol[j] = E + (int64_t)(k0 - kNBO + kq) * ld + min(col, c_end - 1);
+            }
+            T av[2][4], bv[2][4][kBC / 16];
+            auto load_step = [&](int kb, T (&ra)[4], T (&rb_)[4][kBC / 16]) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    av[q] = arow[kb + 4 * q];
+                    ra[q] = arow[kb + 4 * q];
 #pragma unroll
-                    for (int j = 0; j < kBC / 16; ++j)
-                        bv[q][j] = (c0 + 16 * j + cl < c_end) ? bcol[(int64_t)(kb + 4 * q) * ld + 16 * j] : T(0);
+                    for (int j = 0; j < kBC / 16; ++j) rb_[q][j] = bcol[j][(int64_t)(kb + 4 * q) * ld];
                 }
+            };
+            load_step(0, av[0], bv[0]);
+#pragma unroll
+            for (int s8 = 0; s8 < kNBO / 16; ++s8) {
+                const int cur = s8 & 1;
+                if (s8 + 1 < kNBO / 16) load_step(16 * (s8 + 1), av[cur ^ 1], bv[cur ^ 1]);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int j = 0; j < kBC / 16; ++j) a[j] = MF<T>::mfma(av[q], bv[q][j], a[j]);
+                    for (int j = 0; j < kBC / 16; ++j)
+                        a[j] = MF<T>::mfma(av[cur][q], cok[j] ? bv[cur][q][j] : T(0), a[j]);
             }
 #pragma unroll
             for (int j = 0; j < kBC / 16; ++j)
