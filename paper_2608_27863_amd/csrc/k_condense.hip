@@ -1674,19 +1674,27 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
         buf ^= 1;
         ch = nx;
     }
-    // epilogue: out = Cin - product
+    // epilogue: out = Cin - product; the 16 Cin values of a row block are loaded
+    // together from clamped in-range addresses before any of them is used
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < 4; ++bi) {
+        double cv[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = min(r0 + wr + 16 * bi + MF<double>::rowof(lane, j), Mrows - 1);
+            const double *cin = E + (int64_t)(arow0 + r) * ld + n;
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) cv[j][bj] = cin[min(c0 + wc + 16 * bj + (lane & 15), N - 1)];
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = r0 + wr + 16 * bi + MF<double>::rowof(lane, j);
             if (r >= Mrows) continue;
-            const double *cin = E + (int64_t)(arow0 + r) * ld + n;
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj) {
                 const int c = c0 + wc + 16 * bj + (lane & 15);
                 if (c >= N) continue;
-                const double v = cin[c] - acc[bi][bj][j];
+                const double v = cv[j][bj] - acc[bi][bj][j];
                 if (OP == 0) {
                     float *M = Mbase + (dm.m32_off[e] - dm.m32_off[e0]);
                     M[(int64_t)r * ld + n + c] = (float)v;
@@ -1695,6 +1703,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
                 }
             }
         }
+    }
 }
 
 }  // namespace
