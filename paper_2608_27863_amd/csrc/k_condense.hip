@@ -1026,6 +1026,7 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
             for (int s8 = 0; s8 < kNBO / 16; ++s8) {
                 const int cur = s8 & 1;
                 if (s8 + 1 < kNBO / 16) load_step(16 * (s8 + 1), av[cur ^ 1], bv[cur ^ 1]);
+                __builtin_amdgcn_sched_barrier(0);  // keep the next step's loads ahead of these products
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
