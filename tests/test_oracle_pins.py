@@ -399,3 +399,190 @@ def test_matvec_asm_and_gmres_against_dense():
     Kb = np.array(Kb).T
     c, *_ = np.linalg.lstsq(Minv @ S @ Kb, Minv @ ts.g, rcond=None)
     assert np.linalg.norm(Kb @ c - xm) < 1e-8 * np.linalg.norm(xm)
+
+
+# ------------------------------------------- stress, viscous work, tau, walls
+def _primitive_to_conserved(rho, v, e, drho, dv, de):
+    """Conserved state w and gradient q = grad w from primitive values and
+    gradients (rho, v_i, e; d_j rho, d_j v_i [i][j], d_j e), by the product
+    rule on w = (rho, rho v, rho (e + |v|^2/2)).  Input construction only."""
+    v = np.asarray(v, float)
+    dv = np.asarray(dv, float)
+    drho = np.asarray(drho, float)
+    de = np.asarray(de, float)
+    E = e + 0.5 * v @ v
+    w = np.array([rho, *(rho * v), rho * E])
+    q = np.zeros((5, 3))
+    q[0] = drho
+    for i in range(3):
+        q[1 + i] = v[i] * drho + rho * dv[i]
+    dE = de + v @ dv  # d_j E = d_j e + v_k d_j v_k
+    q[4] = E * drho + rho * dE
+    return w, q.ravel()
+
+
+def _mu_star(e, mach=1.25, re=1600.0):
+    g = GOLD["sutherland_nondimensional"]
+    T = 1.4 * 0.4 * mach ** 2 * e
+    return g["c1"] * T ** 1.5 / (T + g["c2"]) / re
+
+
+def test_stress_follows_stokes_hypothesis():
+    """Eq. stress-heat with beta = 0 (Stokes' hypothesis): an isotropic
+    dilatation grad v = c I and a rigid rotation (antisymmetric grad v) carry
+    no viscous stress; a uniaxial strain d v1/dx = s gives the textbook
+    normal stresses tau_11 = 4/3 mu s, tau_22 = tau_33 = -2/3 mu s; the stress
+    is trace-free for any gradient."""
+    rng = np.random.default_rng(11)
+    rho, e = 1.1, 0.45
+    v = np.array([0.3, -0.2, 0.15])
+    mu = _mu_star(e)
+    zero3 = np.zeros(3)
+    # isotropic dilatation, also with density and energy gradients present
+    for c in (0.7, -1.3):
+        for drho in (zero3, rng.standard_normal(3)):
+            w, q = _primitive_to_conserved(rho, v, e, drho, c * np.eye(3), zero3)
+            _, Fv, _, _ = O.point_flux(w, q, 0.0, _prm())
+            assert np.abs(Fv[1:4]).max() < 1e-15 * max(1.0, abs(c)), Fv[1:4]
+            assert np.abs(Fv[4]).max() < 1e-15, Fv[4]  # no stress, no heat flux (de = 0)
+    # rigid rotation
+    Om = np.array([[0.0, -0.8, 0.3], [0.8, 0.0, -1.1], [-0.3, 1.1, 0.0]])
+    w, q = _primitive_to_conserved(rho, v, e, zero3, Om, zero3)
+    _, Fv, _, _ = O.point_flux(w, q, 0.0, _prm())
+    assert np.abs(Fv[1:]).max() < 1e-15
+    # uniaxial strain: the 4/3 and -2/3 normal stresses
+    s = 0.9
+    dv = np.zeros((3, 3))
+    dv[0, 0] = s
+    w, q = _primitive_to_conserved(rho, v, e, zero3, dv, zero3)
+    _, Fv, _, _ = O.point_flux(w, q, 0.0, _prm())
+    tau = Fv[1:4]
+    assert abs(tau[0, 0] - 4.0 / 3.0 * mu * s) < 1e-15
+    assert abs(tau[1, 1] + 2.0 / 3.0 * mu * s) < 1e-15
+    assert abs(tau[2, 2] + 2.0 / 3.0 * mu * s) < 1e-15
+    assert np.abs(tau - np.diag(np.diag(tau))).max() < 1e-16
+    # trace-free and symmetric for a random gradient
+    for _ in range(5):
+        w, q = _primitive_to_conserved(rho, v, e, rng.standard_normal(3), rng.standard_normal((3, 3)),
+                                       rng.standard_normal(3))
+        _, Fv, _, _ = O.point_flux(w, q, 0.0, _prm())
+        tau = Fv[1:4]
+        assert abs(np.trace(tau)) < 1e-15 * np.abs(tau).max() * 10
+        assert np.allclose(tau, tau.T, rtol=0, atol=1e-16)
+
+
+def test_viscous_work_in_energy_flux():
+    """Energy row of eq. viscous-flux, v_i tau_ij + f_j: under a Galilean boost
+    v -> v + V (gradients of v and e unchanged, so T, mu and tau unchanged) the
+    momentum viscous flux is unchanged and the energy viscous flux changes by
+    exactly V_i tau_ij.  Hand value: simple shear d v1/dy = s at v = (V, 0, 0)
+    with no energy gradient gives an energy flux V mu s in y, 0 in x and z."""
+    rng = np.random.default_rng(12)
+    rho, e = 0.95, 0.5
+    mu = _mu_star(e)
+    s, V = 0.6, 0.35
+    dv = np.zeros((3, 3))
+    dv[0, 1] = s
+    w, q = _primitive_to_conserved(rho, [V, 0.0, 0.0], e, np.zeros(3), dv, np.zeros(3))
+    _, Fv, _, _ = O.point_flux(w, q, 0.0, _prm())
+    assert abs(Fv[1, 1] - mu * s) < 1e-15 and abs(Fv[2, 0] - mu * s) < 1e-15
+    assert abs(Fv[4, 1] - V * mu * s) < 1e-16
+    assert abs(Fv[4, 0]) < 1e-16 and abs(Fv[4, 2]) < 1e-16
+    for _ in range(4):
+        v0 = rng.uniform(-0.4, 0.4, 3)
+        Vb = rng.uniform(-0.5, 0.5, 3)
+        drho, dvr, der = rng.standard_normal(3), rng.standard_normal((3, 3)), rng.standard_normal(3)
+        w0, q0 = _primitive_to_conserved(rho, v0, e, drho, dvr, der)
+        w1, q1 = _primitive_to_conserved(rho, v0 + Vb, e, drho, dvr, der)
+        _, F0, _, _ = O.point_flux(w0, q0, 0.0, _prm())
+        _, F1, _, _ = O.point_flux(w1, q1, 0.0, _prm())
+        sc = np.abs(F0).max()
+        assert np.allclose(F1[1:4], F0[1:4], rtol=0, atol=1e-14 * sc)
+        assert np.allclose(F1[4] - F0[4], Vb @ F0[1:4], rtol=0, atol=1e-14 * sc)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_stabilisation_term_of_trace_rows(p):
+    """Eq. num-flux-hdg: F^c(uhat) and F^v(uhat, q) do not depend on the
+    element state u, so the u-columns of C = dR_uh^K/dU come from the
+    stabilisation term tau (u - uhat) alone: by the partition of unity of the
+    volume and trace bases, summing a face's rows of component c over its
+    nodes and the u_c' columns over the element's nodes gives +tau |F| for
+    c = c' and 0 otherwise (|F| = h^2 on a straight cube)."""
+    n = 2
+    wl = _wl(n=n, p=p, perturb=0.0, nu_amp=5e-4, mach=1.25)
+    sz = O.Sizes(wl.mesh)
+    area = (2 * math.pi / n) ** 2
+    Np = (p + 1) ** 3
+    nfp = (p + 1) ** 2
+    for e in (0, 5):
+        E = O.element_system(wl, e, sz)
+        nn = sz.n(e)
+        C = E[nn:, :nn]
+        for lf in range(6):
+            r0 = nn + lf * 5 * nfp
+            for c in range(5):
+                rows = E[r0 + c * nfp:r0 + (c + 1) * nfp, :nn]
+                for c2 in range(5):
+                    ssum = rows[:, (15 + c2) * Np:(16 + c2) * Np].sum()
+                    want = wl.tau * area if c == c2 else 0.0
+                    assert abs(ssum - want) < 1e-12 * wl.tau * area, (e, lf, c, c2, ssum)
+        assert C.shape[0] == 30 * nfp
+
+
+def test_dirichlet_faces():
+    """Boundary faces of eq. hdg-trace with the prescribed-state reading: the
+    trace equation is int_F (uhat - u_b) mu_a.  On a box with walls at y = 0 and
+    y = L_y, a uniform state with uhat = u_b = u has a zero residual everywhere
+    (the interior rows by free-stream preservation, the wall rows because
+    uhat = u_b).  With uhat - u_b = delta constant on a wall face, the face's
+    rows of component c sum to delta_c |F|; their C rows vanish and their D
+    block is the face mass matrix (sum |F| per component, no coupling between
+    components)."""
+    p = 2
+    nx, ny, nz = 2, 2, 2
+    L = (2 * math.pi, 1.5, 2 * math.pi)
+    mesh = synth.box_mesh((nx, ny, nz), lengths=L, periodic=(True, False, True), p=p, perturb=0.1, seed=3)
+    const = np.array(synth._conserved(1.05, 0.25, 0.0, -0.1, 0.8))
+    field = lambda x: np.broadcast_to(const, x.shape[:-1] + (5,)) + 0.0 * x[..., :1]
+    wl = synth.make_state(mesh, field, mach=1.25, noise=0.0, nu_amp=5e-4, seed=3, boundary_field=field)
+    wl.Q[:] = 0.0
+    sz = O.Sizes(mesh)
+    Rh = np.zeros(wl.Uhat.shape)
+    for e in range(mesh.n_elem):
+        E = O.element_system(wl, e, sz)
+        nn = sz.n(e)
+        assert np.abs(E[:nn, -1]).max() < 1e-13
+        t = np.concatenate([[0], np.cumsum(sz.face_sizes(e))])
+        for a, F in enumerate(mesh.elem_face[e]):
+            Rh[sz.foff[F]:sz.foff[F + 1]] += E[nn + t[a]:nn + t[a + 1], -1]
+    assert mesh.face_bc.sum() == 2 * nx * nz
+    assert np.abs(Rh).max() < 1e-13
+    # constant offset delta on every wall face (uhat - u_b = delta)
+    delta = np.array([1e-2, -2e-2, 3e-2, 5e-3, -1e-2])
+    nfp = (p + 1) ** 2
+    Uh = wl.Uhat.copy()
+    for F in np.nonzero(mesh.face_bc)[0]:
+        Uh[sz.foff[F]:sz.foff[F + 1]] += np.repeat(delta, nfp)
+    hx, hz = L[0] / nx, L[2] / nz  # wall faces are flat rectangles (wall vertices are not perturbed)
+    for e in range(mesh.n_elem):
+        E = O.element_system(wl, e, sz, Uhat=Uh)
+        nn = sz.n(e)
+        for lf, F in enumerate(mesh.elem_face[e]):
+            if not mesh.face_bc[F]:
+                continue
+            r0 = nn + lf * 5 * nfp
+            for c in range(5):
+                rows = slice(r0 + c * nfp, r0 + (c + 1) * nfp)
+                assert abs(E[rows, -1].sum() - delta[c] * hx * hz) < 1e-13
+                assert not np.any(E[rows, :nn])
+                for c2 in range(5):
+                    Dcc = E[rows, nn + lf * 5 * nfp + c2 * nfp:nn + lf * 5 * nfp + (c2 + 1) * nfp]
+                    if c2 == c:
+                        assert abs(Dcc.sum() - hx * hz) < 1e-13 and np.allclose(Dcc, Dcc.T, atol=1e-16)
+                    else:
+                        assert not np.any(Dcc)
+                # no coupling to the element's other faces
+                other = np.ones(E.shape[0] - nn, bool)
+                other[lf * 5 * nfp:(lf + 1) * 5 * nfp] = False
+                assert not np.any(E[rows, nn:-1][:, other])
