@@ -200,7 +200,13 @@ int hdg_condense(hdg_ctx *ctx, int prec, int refine_steps, int e0, int ne, doubl
  */
 int hdg_assemble_trace(hdg_ctx *ctx, const double *SK, double *S_bsr, double *g, void *stream);
 
-/* y = S x over the block-sparse operator (a trace-space matvec inside GMRES). */
+/*
+ * y = S x with the assembled condensed trace operator S of eq. schur-trace
+ * (section 3.2: the operator is assembled once per Newton iteration and
+ * applied in every Krylov iteration).  S_bsr in the block-sparse layout above
+ * (all blocks of the pattern); x, y face arrays of length N_uh; x and y must
+ * not alias.  Reads S once: bound by HBM bandwidth.
+ */
 int hdg_face_matvec(hdg_ctx *ctx, const double *S_bsr, const double *x, double *y, void *stream);
 
 /*
@@ -241,6 +247,65 @@ int hdg_gmres(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, con
  */
 int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E,
                          const double *dUhat, double *dQU, void *stream);
+
+/*
+ * The whole hot path of one Newton iteration (figure "Computational workflow":
+ * element residuals and Jacobians, static condensation, assembly of S and g,
+ * additive-Schwarz set-up, preconditioned GMRES, interior recovery; sections
+ * 2.4-3.3) as one call, and as a HIP graph.
+ *
+ * hdg_newton_args names every buffer of the step; all pointers except
+ * chunk_e0 / chunk_ne (host) are device memory owned by the caller.  For each
+ * chunk k (elements chunk_e0[k] .. chunk_e0[k]+chunk_ne[k]-1, every element in
+ * exactly one chunk) the step runs hdg_local_residual_jacobian and
+ * hdg_condense; then hdg_assemble_trace, hdg_asm_setup and hdg_gmres once; then
+ * hdg_recover_interior per chunk.  E holds the systems of all elements
+ * (element e at E_off[e]); qp_work and cond_work must be at least the
+ * workspace of the largest chunk (hdg_workspace_size ops 0 and 1), asm_work
+ * op 2 with asm_prec, gmres_work op 4 with ne = gmres_m.  Ub may be NULL only
+ * on a mesh without Dirichlet faces.  Sinv holds doubles for asm_prec =
+ * HDG_FP64 and floats for HDG_MIXED.  The chunk arrays are copied.
+ */
+typedef struct hdg_newton_args {
+    int prec;            /* condensation arithmetic, HDG_FP64 or HDG_MIXED          */
+    int refine_steps;    /* HDG_MIXED: refinement steps, 1..8 (ignored for FP64)   */
+    int asm_prec;        /* Schwarz inverses: HDG_FP64 (double) or HDG_MIXED (float)*/
+    int gmres_m;         /* Krylov dimension, 1..200                                */
+    int n_chunks;
+    const int *chunk_e0; /* host [n_chunks]                                         */
+    const int *chunk_ne; /* host [n_chunks]                                         */
+    const double *Q, *U, *Un, *Uhat, *nu, *Ub;
+    double *E;
+    void *qp_work;   size_t qp_work_bytes;
+    void *cond_work; size_t cond_work_bytes;
+    double *SK; int *info;
+    double *S_bsr, *g;
+    void *Sinv; int *asm_info;
+    void *asm_work;   size_t asm_work_bytes;
+    void *gmres_work; size_t gmres_work_bytes;
+    double *dUhat, *res_hist, *dQU;
+} hdg_newton_args;
+
+/* Enqueue the whole step on `stream` (validated first; nothing is enqueued on
+ * an argument error). */
+int hdg_newton_step(hdg_ctx *ctx, const hdg_newton_args *args, void *stream);
+
+typedef struct hdg_graph hdg_graph;
+
+/*
+ * Capture the whole step in a HIP graph and instantiate it.  The step is first
+ * run once on `stream` (this loads every kernel's code object, so that the
+ * capture records launches only; the buffers then hold that step's results),
+ * then recorded with hipStreamBeginCapture / hipStreamEndCapture on `stream`,
+ * which must be a created stream (not NULL, the legacy default stream).
+ * Blocking.  The graph keeps the device pointers of `args`: the buffers must
+ * outlive it, and each launch recomputes the step from their current contents.
+ * On success *out owns the graph (release it with hdg_graph_destroy).
+ */
+int hdg_graph_capture_newton(hdg_ctx *ctx, const hdg_newton_args *args, hdg_graph **out, void *stream);
+/* Enqueue one replay of the captured step on `stream` (any stream, NULL too). */
+int hdg_graph_launch(hdg_graph *graph, void *stream);
+void hdg_graph_destroy(hdg_graph *graph);
 
 #ifdef __cplusplus
 }

@@ -587,4 +587,125 @@ int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E
     return dev_status(hdg::launch_recover(ctx, prec, e0, ne, E, dUhat, dQU, (hipStream_t)stream));
 }
 
+// ------------------------------------------------------ the whole step
+static int newton_check(hdg_ctx *ctx, const hdg_newton_args *a) {
+    if (!ctx || !a) return HDG_ERR_INVALID_ARGUMENT;
+    if ((a->prec != HDG_FP64 && a->prec != HDG_MIXED) || (a->asm_prec != HDG_FP64 && a->asm_prec != HDG_MIXED))
+        return HDG_ERR_INVALID_ARGUMENT;
+    if (a->prec == HDG_MIXED && (a->refine_steps < 1 || a->refine_steps > 8)) return HDG_ERR_INVALID_ARGUMENT;
+    if (a->gmres_m < 1 || a->gmres_m > 200) return HDG_ERR_INVALID_ARGUMENT;
+    if (a->n_chunks < 1 || !a->chunk_e0 || !a->chunk_ne) return HDG_ERR_INVALID_ARGUMENT;
+    if (!a->Q || !a->U || !a->Un || !a->Uhat || !a->nu || !a->E || !a->qp_work || !a->cond_work || !a->SK ||
+        !a->info || !a->S_bsr || !a->g || !a->Sinv || !a->asm_info || !a->asm_work || !a->gmres_work ||
+        !a->dUhat || !a->res_hist || !a->dQU)
+        return HDG_ERR_INVALID_ARGUMENT;
+    // every element in exactly one chunk
+    std::vector<char> seen(ctx->n_elem, 0);
+    for (int k = 0; k < a->n_chunks; ++k) {
+        const int e0 = a->chunk_e0[k], ne = a->chunk_ne[k];
+        if (!chunk_ok(ctx, e0, ne)) return HDG_ERR_INVALID_ARGUMENT;
+        for (int e = e0; e < e0 + ne; ++e) {
+            if (seen[e]) return HDG_ERR_INVALID_ARGUMENT;
+            seen[e] = 1;
+        }
+        size_t need;
+        hdg_workspace_size(ctx, 0, HDG_FP64, e0, ne, &need);
+        if (a->qp_work_bytes < need) return HDG_ERR_WORKSPACE;
+        hdg_workspace_size(ctx, 1, a->prec, e0, ne, &need);
+        if (a->cond_work_bytes < need) return HDG_ERR_WORKSPACE;
+    }
+    for (int e = 0; e < ctx->n_elem; ++e)
+        if (!seen[e]) return HDG_ERR_INVALID_ARGUMENT;
+    if (!a->Ub)
+        for (int F = 0; F < ctx->n_face; ++F)
+            if (ctx->face_bc[F]) return HDG_ERR_INVALID_ARGUMENT;
+    if (ctx->repeated_face) return HDG_ERR_UNSUPPORTED;
+    if (a->asm_work_bytes < hdg::asm_setup_work_bytes(ctx, a->asm_prec)) return HDG_ERR_WORKSPACE;
+    if (a->gmres_work_bytes < hdg::gmres_work_bytes(ctx, a->gmres_m)) return HDG_ERR_WORKSPACE;
+    return HDG_OK;
+}
+
+// The step's calls in order (arguments already checked).
+static int newton_enqueue(hdg_ctx *ctx, const hdg_newton_args *a, void *stream) {
+    int rc;
+    auto Ek = [&](int e0) { return a->E + ctx->E_off[e0]; };
+    for (int k = 0; k < a->n_chunks; ++k) {
+        const int e0 = a->chunk_e0[k], ne = a->chunk_ne[k];
+        if ((rc = hdg_local_residual_jacobian(ctx, e0, ne, a->Q, a->U, a->Un, a->Uhat, a->nu, a->Ub, Ek(e0),
+                                              a->qp_work, a->qp_work_bytes, stream)))
+            return rc;
+        if ((rc = hdg_condense(ctx, a->prec, a->refine_steps, e0, ne, Ek(e0), a->SK, a->info, a->cond_work,
+                               a->cond_work_bytes, stream)))
+            return rc;
+    }
+    if ((rc = hdg_assemble_trace(ctx, a->SK, a->S_bsr, a->g, stream))) return rc;
+    if ((rc = hdg_asm_setup(ctx, a->asm_prec, a->S_bsr, a->Sinv, a->asm_info, a->asm_work, a->asm_work_bytes,
+                            stream)))
+        return rc;
+    if ((rc = hdg_gmres(ctx, a->asm_prec, a->S_bsr, a->Sinv, a->g, a->gmres_m, a->dUhat, a->res_hist,
+                        a->gmres_work, a->gmres_work_bytes, stream)))
+        return rc;
+    for (int k = 0; k < a->n_chunks; ++k) {
+        const int e0 = a->chunk_e0[k], ne = a->chunk_ne[k];
+        if ((rc = hdg_recover_interior(ctx, a->prec, e0, ne, Ek(e0), a->dUhat, a->dQU, stream))) return rc;
+    }
+    return HDG_OK;
+}
+
+int hdg_newton_step(hdg_ctx *ctx, const hdg_newton_args *args, void *stream) {
+    const int rc = newton_check(ctx, args);
+    if (rc) return rc;
+    return newton_enqueue(ctx, args, stream);
+}
+
+}  // extern "C"
+
+struct hdg_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+void hdg_graph_destroy(hdg_graph *gr) {
+    if (!gr) return;
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+}
+
+int hdg_graph_capture_newton(hdg_ctx *ctx, const hdg_newton_args *args, hdg_graph **out, void *stream) {
+    if (!out || !stream) return HDG_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    int rc = newton_check(ctx, args);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // one eager run: every kernel's code object is loaded before the capture
+    if ((rc = newton_enqueue(ctx, args, stream))) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return HDG_ERR_DEVICE;
+    hdg_graph *gr = new (std::nothrow) hdg_graph();
+    if (!gr) return HDG_ERR_OUT_OF_MEMORY;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        delete gr;
+        return HDG_ERR_DEVICE;
+    }
+    rc = newton_enqueue(ctx, args, stream);
+    const hipError_t end = hipStreamEndCapture(s, &gr->graph);
+    if (rc || end != hipSuccess || !gr->graph) {
+        hdg_graph_destroy(gr);
+        return rc ? rc : HDG_ERR_DEVICE;
+    }
+    if (hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess) {
+        hdg_graph_destroy(gr);
+        return HDG_ERR_DEVICE;
+    }
+    *out = gr;
+    return HDG_OK;
+}
+
+int hdg_graph_launch(hdg_graph *gr, void *stream) {
+    if (!gr || !gr->exec) return HDG_ERR_INVALID_ARGUMENT;
+    return hipGraphLaunch(gr->exec, (hipStream_t)stream) == hipSuccess ? HDG_OK : HDG_ERR_DEVICE;
+}
+
 }  // extern "C"

@@ -24,7 +24,8 @@ LAYOUT = {"node_off": 0, "face_off": 1, "E_off": 2, "SK_off": 3, "bsr_row_ptr": 
 
 EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_layout_length",
            "hdg_workspace_size", "hdg_local_residual_jacobian", "hdg_condense", "hdg_assemble_trace",
-           "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior"]
+           "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior",
+           "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy"]
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -44,6 +45,18 @@ class _Phys(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("reynolds", ctypes.c_double),
                 ("mach", ctypes.c_double), ("tau", ctypes.c_double), ("dt", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("visc_law", _i)]
+
+
+class _NewtonArgs(ctypes.Structure):
+    _fields_ = [("prec", _i), ("refine_steps", _i), ("asm_prec", _i), ("gmres_m", _i), ("n_chunks", _i),
+                ("chunk_e0", _vp), ("chunk_ne", _vp),
+                ("Q", _vp), ("U", _vp), ("Un", _vp), ("Uhat", _vp), ("nu", _vp), ("Ub", _vp),
+                ("E", _vp), ("qp_work", _vp), ("qp_work_bytes", ctypes.c_size_t),
+                ("cond_work", _vp), ("cond_work_bytes", ctypes.c_size_t),
+                ("SK", _vp), ("info", _vp), ("S_bsr", _vp), ("g", _vp),
+                ("Sinv", _vp), ("asm_info", _vp), ("asm_work", _vp), ("asm_work_bytes", ctypes.c_size_t),
+                ("gmres_work", _vp), ("gmres_work_bytes", ctypes.c_size_t),
+                ("dUhat", _vp), ("res_hist", _vp), ("dQU", _vp)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -71,8 +84,13 @@ def load_library(path: str = LIB_PATH):
     L.hdg_asm_block_apply.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.hdg_gmres.argtypes = [_vp, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.hdg_recover_interior.argtypes = [_vp, _i, _i, _i, _vp, _vp, _vp, _vp]
+    L.hdg_newton_step.argtypes = [_vp, ctypes.POINTER(_NewtonArgs), _vp]
+    L.hdg_graph_capture_newton.argtypes = [_vp, ctypes.POINTER(_NewtonArgs), ctypes.POINTER(_vp), _vp]
+    L.hdg_graph_launch.argtypes = [_vp, _vp]
+    L.hdg_graph_destroy.argtypes = [_vp]
+    L.hdg_graph_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length"):
+        if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length", "hdg_graph_destroy"):
             getattr(L, name).restype = _i
     _lib = L
     return L
@@ -239,3 +257,64 @@ class Context:
                                          _ptr(dUhat, torch.float64, self.N_uh, "dUhat"),
                                          _ptr(dQU, torch.float64, 20 * nn, "dQU"), _stream(stream))
         _check(rc, "hdg_recover_interior")
+
+    # ------------------------------------------------------- whole step
+    def newton_args(self, st):
+        """hdg_newton_args for a pipeline.NewtonStep's buffers (the struct and
+        the host chunk arrays are kept alive on the returned object)."""
+        import torch
+        f64 = torch.float64
+        nn = int(self.layout["node_off"][-1])
+        e0 = np.ascontiguousarray([c[0] for c in st.chunks], dtype=np.int32)
+        ne = np.ascontiguousarray([c[1] for c in st.chunks], dtype=np.int32)
+        nb = lambda t: t.numel() * t.element_size()
+        a = _NewtonArgs(
+            st.prec, st.refine, st.asm_prec, st.m, len(st.chunks), e0.ctypes.data, ne.ctypes.data,
+            _ptr(st.Q, f64, 15 * nn, "Q"), _ptr(st.U, f64, 5 * nn, "U"), _ptr(st.Un, f64, 5 * nn, "Un"),
+            _ptr(st.Uhat, f64, self.N_uh, "Uhat"), _ptr(st.nu, f64, nn, "nu"),
+            _ptr(st.Ub, f64, self.N_uh, "Ub") if st.Ub is not None else None,
+            _ptr(st.E, f64, int(self.layout["E_off"][-1]), "E"), _ptr(st.qp_work), nb(st.qp_work),
+            _ptr(st.cond_work), nb(st.cond_work),
+            _ptr(st.SK, f64, int(self.layout["SK_off"][-1]), "SK"), _ptr(st.info, torch.int32, self.n_elem, "info"),
+            _ptr(st.S, f64, int(self.layout["bsr_val_off"][-1]), "S"), _ptr(st.g, f64, self.N_uh, "g"),
+            _ptr(st.Sinv, self._sinv_dtype(st.asm_prec), int(self.layout["asm_off"][-1]), "Sinv"),
+            _ptr(st.asm_info, torch.int32, self.n_elem, "asm_info"), _ptr(st.asm_work), nb(st.asm_work),
+            _ptr(st.gm_work), nb(st.gm_work),
+            _ptr(st.dUhat, f64, self.N_uh, "dUhat"), _ptr(st.hist, f64, st.m + 1, "res_hist"),
+            _ptr(st.dQU, f64, 20 * nn, "dQU"))
+        a._keep = (e0, ne)
+        return a
+
+    def hdg_newton_step(self, args, stream=None):
+        _check(self.L.hdg_newton_step(self.h, ctypes.byref(args), _stream(stream)), "hdg_newton_step")
+
+    def hdg_graph_capture_newton(self, args, stream):
+        """Capture the whole step on `stream` (a created torch.cuda.Stream, not
+        the default stream); returns a Graph."""
+        g = _vp()
+        _check(self.L.hdg_graph_capture_newton(self.h, ctypes.byref(args), ctypes.byref(g), _stream(stream)),
+               "hdg_graph_capture_newton")
+        return Graph(self, g, args)
+
+
+class Graph:
+    """A captured Newton step (hdg_graph); replay() enqueues one launch."""
+
+    def __init__(self, ctx, handle, args):
+        self.ctx = ctx
+        self.h = handle
+        self._args = args  # the captured pointers belong to these buffers
+
+    def replay(self, stream=None):
+        _check(self.ctx.L.hdg_graph_launch(self.h, _stream(stream)), "hdg_graph_launch")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.L.hdg_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,8 +2,10 @@
 
 Allocates the device buffers (torch) and issues, on one stream:
   hdg_local_residual_jacobian (per chunk) -> hdg_condense (per chunk)
-  -> hdg_assemble_trace -> hdg_asm_setup -> hdg_gmres -> hdg_recover_interior.
-No arithmetic happens here; every step runs in libhdg's kernels.
+  -> hdg_assemble_trace -> hdg_asm_setup -> hdg_gmres -> hdg_recover_interior,
+either call by call or as one hdg_newton_step, or replayed from a HIP graph the
+library captures (hdg_graph_capture_newton).  No arithmetic happens here;
+every step runs in libhdg's kernels.
 """
 from __future__ import annotations
 
@@ -102,7 +104,13 @@ class NewtonStep:
             self.ctx.hdg_recover_interior(self.prec, e0, n, self.E_chunk(e0, n), self.dUhat, self.dQU, stream)
 
     def run(self, stream=None):
-        """The whole hot path for one Newton step."""
+        """The whole hot path for one Newton step, as one call (hdg_newton_step)."""
+        if getattr(self, "_args", None) is None:
+            self._args = self.ctx.newton_args(self)
+        self.ctx.hdg_newton_step(self._args, stream)
+
+    def run_calls(self, stream=None):
+        """The same step issued call by call from here."""
         self.residual_jacobian(stream)
         self.condense(stream)
         self.assemble(stream)
@@ -110,15 +118,17 @@ class NewtonStep:
         self.gmres(stream)
         self.recover(stream)
 
-    def capture(self):
-        """The whole Newton step captured once in a HIP graph (torch.cuda.CUDAGraph).
-        Every launch of the step goes to the capturing stream; nothing is
-        allocated or synchronised inside.  graph.replay() reruns the step on the
-        current contents of the input buffers."""
+    def capture(self, stream=None):
+        """The whole Newton step captured in a HIP graph by the library
+        (hdg_graph_capture_newton) on `stream`, a created stream (a new one when
+        None).  Blocking.  graph.replay(stream) reruns the step on the current
+        contents of the input buffers; nothing is allocated or synchronised
+        inside."""
         import torch
-        self.run()  # first launches outside the capture (lazy loading of the code objects)
+        if getattr(self, "_args", None) is None:
+            self._args = self.ctx.newton_args(self)
+        s = stream if stream is not None else torch.cuda.Stream()
         torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            self.run()
+        graph = self.ctx.hdg_graph_capture_newton(self._args, s)
+        torch.cuda.synchronize()
         return graph
