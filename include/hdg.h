@@ -229,6 +229,23 @@ int hdg_asm_block_apply(hdg_ctx *ctx, int prec, const void *Sinv, const double *
                         void *work, size_t work_bytes, void *stream);
 
 /*
+ * hdg_asm_block_apply for callers that cannot allocate device memory (code
+ * under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same z = sum_r R_r^T S_r^{-1} R_r r with the same kernels, but
+ * the element-local corrections live in a library-owned device array of
+ * HDG_ASM_NOALLOC_MAX_DOUBLES doubles (32 MiB) instead of a caller workspace.
+ * Each GPU the library runs on holds one such array from hdg_create until the
+ * process ends.  Returns HDG_ERR_WORKSPACE when the mesh needs more than that
+ * (sum over elements of f_e > HDG_ASM_NOALLOC_MAX_DOUBLES, e.g. more than
+ * 5592 elements of degree 4).  Allocates nothing.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads, other contexts) race and must be serialised by the caller.
+ */
+#define HDG_ASM_NOALLOC_MAX_DOUBLES 4194304
+int hdg_asm_block_apply_noalloc(hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
+                                void *stream);
+
+/*
  * One cycle of left-preconditioned GMRES(m) on S dUhat = g, x0 = 0
  * (section 3.2): Arnoldi with classical Gram-Schmidt applied twice, Givens
  * rotations and the triangular solve on the device, all FP64.  res_hist

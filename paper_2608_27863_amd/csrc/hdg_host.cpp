@@ -411,6 +411,7 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
     }
     // ---- upload (first HIP call: everything above is host-side validation and set-up)
     if (hipGetDevice(&ctx->device) != hipSuccess) return fail(HDG_ERR_DEVICE);
+    if (hdg::asm_scratch_init(ctx->device) != 0) return fail(HDG_ERR_DEVICE);
     DevMesh &dm = ctx->dm;
     dm.n_elem = ne;
     dm.n_face = nf;
@@ -569,6 +570,13 @@ int hdg_asm_block_apply(hdg_ctx *ctx, int prec, const void *Sinv, const double *
     if (!ctx || !Sinv || !r || !z || r == z || (prec != HDG_FP64 && prec != HDG_MIXED)) return HDG_ERR_INVALID_ARGUMENT;
     if (work_bytes < hdg::asm_apply_work_bytes(ctx) || !work) return HDG_ERR_WORKSPACE;
     return dev_status(hdg::launch_asm_apply(ctx, prec, Sinv, r, z, work, (hipStream_t)stream));
+}
+
+int hdg_asm_block_apply_noalloc(hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
+                                void *stream) {
+    if (!ctx || !Sinv || !r || !z || r == z || (prec != HDG_FP64 && prec != HDG_MIXED)) return HDG_ERR_INVALID_ARGUMENT;
+    if ((size_t)ctx->tloc_off[ctx->n_elem] > hdg::kAsmScratchDoubles) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_asm_apply_noalloc(ctx, prec, Sinv, r, z, (hipStream_t)stream));
 }
 
 int hdg_gmres(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, const double *g, int m,

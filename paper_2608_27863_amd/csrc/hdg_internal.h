@@ -123,6 +123,11 @@ size_t schwarz_ws_bytes(const hdg_ctx *ctx, int prec);
 int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
                      void *work, hipStream_t s);
 size_t asm_apply_work_bytes(const hdg_ctx *ctx);
+// hdg_asm_block_apply_noalloc: a per-device library array holds zloc.
+constexpr size_t kAsmScratchDoubles = HDG_ASM_NOALLOC_MAX_DOUBLES;  // 32 MiB
+int asm_scratch_init(int device);
+int launch_asm_apply_noalloc(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
+                             hipStream_t s);
 int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv, const double *g,
                  int m, double *x, double *hist, void *work, hipStream_t s);
 size_t gmres_work_bytes(const hdg_ctx *ctx, int m);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "hdg_internal.h"
 
@@ -498,6 +499,41 @@ int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const doubl
         hipLaunchKernelGGL(k_asm_local<float>, grid, dim3(256), 0, s, dm, (const float *)Sinv, r, zloc);
     hipLaunchKernelGGL(k_asm_gather, dim3(ctx->n_face), dim3(128), 0, s, dm, (const double *)zloc, z);
     return (int)hipGetLastError();
+}
+
+// Workspace of hdg_asm_block_apply_noalloc: the element-local corrections
+// zloc (sum of f_e doubles) in a library-owned array, one copy per device.
+// Host code never passes `scratch` itself to a kernel (on the host the name
+// is only a stand-in): it passes the device address recorded per device by
+// asm_scratch_init.
+static __device__ __align__(256) double scratch[kAsmScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int asm_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return 0;
+    double *ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || !ptr) return err != hipSuccess ? (int)err : (int)hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return 0;
+}
+
+int launch_asm_apply_noalloc(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
+                             hipStream_t s) {
+    double *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (ctx->device >= 0 && ctx->device < kMaxDevices) ptr = g_scratch_ptr[ctx->device];
+    }
+    if (!ptr) return (int)hipErrorInvalidSymbol;
+    return launch_asm_apply(ctx, prec, Sinv, r, z, ptr, s);
 }
 
 // GMRES workspace (doubles): V[(m+1) N] | w[N] | t[N] | zloc | H[(m+1) m] | cs[m] | sn[m] | gam[m+1] |

@@ -25,7 +25,8 @@ LAYOUT = {"node_off": 0, "face_off": 1, "E_off": 2, "SK_off": 3, "bsr_row_ptr": 
 EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_layout_length",
            "hdg_workspace_size", "hdg_local_residual_jacobian", "hdg_condense", "hdg_assemble_trace",
            "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior",
-           "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy"]
+           "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy",
+           "hdg_asm_block_apply_noalloc"]
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     L.hdg_graph_launch.argtypes = [_vp, _vp]
     L.hdg_graph_destroy.argtypes = [_vp]
     L.hdg_graph_destroy.restype = None
+    L.hdg_asm_block_apply_noalloc.argtypes = [_vp, _i, _vp, _vp, _vp, _vp]
     for name in EXPORTS:
         if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length", "hdg_graph_destroy"):
             getattr(L, name).restype = _i
@@ -257,6 +259,13 @@ class Context:
                                          _ptr(dUhat, torch.float64, self.N_uh, "dUhat"),
                                          _ptr(dQU, torch.float64, 20 * nn, "dQU"), _stream(stream))
         _check(rc, "hdg_recover_interior")
+
+    def hdg_asm_block_apply_noalloc(self, prec, Sinv, r, z, stream=None):
+        import torch
+        rc = self.L.hdg_asm_block_apply_noalloc(
+            self.h, prec, _ptr(Sinv, self._sinv_dtype(prec), int(self.layout["asm_off"][-1]), "Sinv"),
+            _ptr(r, torch.float64, self.N_uh, "r"), _ptr(z, torch.float64, self.N_uh, "z"), _stream(stream))
+        _check(rc, "hdg_asm_block_apply_noalloc")
 
     # ------------------------------------------------------- whole step
     def newton_args(self, st):
