@@ -146,9 +146,11 @@ int hdg_layout(const hdg_ctx *ctx, int kind, int64_t *dst, int64_t capacity);
 int64_t hdg_layout_length(const hdg_ctx *ctx, int kind);
 
 /* Workspace sizes in bytes (caller allocates, 256-byte aligned).  `op` is the
- * entry point: 1 hdg_condense (for a chunk of ne elements starting at e0),
- * 2 hdg_asm_setup, 3 hdg_asm_block_apply, 4 hdg_gmres (with Krylov dimension
- * m = ne). */
+ * entry point: 0 hdg_local_residual_jacobian and 1 hdg_condense (for a chunk
+ * of ne elements starting at e0), 2 hdg_asm_setup, 3 hdg_asm_block_apply,
+ * 4 hdg_gmres / hdg_gmres_x0 (with Krylov dimension m = ne), 5 hdg_rb_guess
+ * (with ne = the largest basis size used), 6 hdg_residual_gather /
+ * hdg_residual_norm. */
 int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, size_t *bytes);
 
 /*
@@ -255,6 +257,78 @@ int hdg_asm_block_apply_noalloc(hdg_ctx *ctx, int prec, const void *Sinv, const 
 int hdg_gmres(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, const double *g,
               int m, double *dUhat, double *res_hist, void *work, size_t work_bytes,
               void *stream);
+
+/*
+ * GMRES(m) started from an initial guess x0 (device, N_uh): as hdg_gmres, but
+ * the cycle minimises ||M^{-1}(g - S x)||_2 over x0 + K_m(M^{-1} S, r0) with
+ * r0 = M^{-1}(g - S x0) (section 3.2; the reduced basis of section 3.4 supplies
+ * x0).  res_hist[0] = ||r0||.  dUhat may alias x0.  Workspace op 4.
+ */
+int hdg_gmres_x0(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, const double *g, const double *x0,
+                 int m, double *dUhat, double *res_hist, void *work, size_t work_bytes, void *stream);
+
+/*
+ * Reduced-basis initial guess (section 3.4, eq. rb-min).  W and Z are device
+ * arrays of column vectors of length N_uh (column j at j * N_uh): W holds
+ * previously accepted trace corrections w_j and Z their products z_j = S w_j,
+ * taken with the trace operator of the iteration that accepted them.  With the
+ * first nb columns:
+ *   c = argmin_c || g - Z c ||_2,   x0 = W c.
+ * Computed by classical Gram-Schmidt QR of Z (two projections per column) and
+ * c = R^{-1} Q^T g; a column whose part orthogonal to the previous ones is
+ * below 1e-12 of its norm is dependent on them and gets c_j = 0 (the kept
+ * columns span the same space, so the minimal residual is the same).  nb = 0
+ * gives x0 = 0 (W, Z, work may be NULL).  0 <= nb <= HDG_RB_MAX.  Workspace
+ * op 5 with ne = nb (or the largest nb used).
+ */
+#define HDG_RB_MAX 32
+int hdg_rb_guess(hdg_ctx *ctx, int nb, const double *W, const double *Z, const double *g, double *x0, void *work,
+                 size_t work_bytes, void *stream);
+
+/*
+ * Insert an accepted trace correction into the reduced basis (section 3.4):
+ * the window of at most nb_max columns is first-in first-out.  W[:, *head] =
+ * w_new and Z[:, *head] = S w_new (one application of the trace operator),
+ * then *head = (*head + 1) mod nb_max and *count = min(*count + 1, nb_max),
+ * so that once the window is full the oldest column is the one replaced.
+ * count and head are host ints (in/out); 1 <= nb_max <= HDG_RB_MAX.
+ */
+int hdg_rb_insert(hdg_ctx *ctx, const double *S_bsr, const double *w_new, int nb_max, int *count, int *head,
+                  double *W, double *Z, void *stream);
+
+/*
+ * Newton update of the stage state (eq. newton-update): Q += alpha dQ,
+ * U += alpha dU (dQU packed as in hdg_recover_interior) and Uhat += alpha dUhat.
+ */
+int hdg_state_update(hdg_ctx *ctx, double alpha, const double *dQU, const double *dUhat, double *Q, double *U,
+                     double *Uhat, void *stream);
+
+/*
+ * Admissibility of the damped update (0 < alpha <= 1 in eq. newton-update):
+ * flag (device int) = 1 if U + alpha dU has a node with non-positive density
+ * or pressure, or a non-finite value; else 0.
+ */
+int hdg_state_admissible(hdg_ctx *ctx, double alpha, const double *U, const double *dQU, int *flag, void *stream);
+
+/*
+ * out = sum_{i<k} coef[i] v[i] over n doubles (1 <= k <= 8; v is a host array
+ * of device pointers, coef host): the stage combinations of the DIRK method,
+ * eqs. dirk-stage (the lagged mass term) and dirk-update.  out may alias any v.
+ */
+int hdg_lincomb(hdg_ctx *ctx, int k, const double *const *v, const double *coef, double *out, int64_t n,
+                void *stream);
+
+/*
+ * Nonlinear residual norm of eq. nonlinear-residual.  hdg_residual_gather, for
+ * elements e0 .. e0+ne-1, reads the residual columns of E just written by
+ * hdg_local_residual_jacobian (before hdg_condense overwrites them) into
+ * `work` (op 6); once every element is gathered, hdg_residual_norm writes
+ * norms[0..2] (device) = ||R_q||_2, ||R_u||_2 and ||R_uh||_2 of the assembled
+ * trace residual R_uh = sum_K P_K^T R_uh^K (eq. trace-residual), with
+ * fixed-order sums (deterministic).
+ */
+int hdg_residual_gather(hdg_ctx *ctx, int e0, int ne, const double *E, void *work, size_t work_bytes, void *stream);
+int hdg_residual_norm(hdg_ctx *ctx, void *work, size_t work_bytes, double *norms, void *stream);
 
 /*
  * Interior recovery (eq. local-elimination): for elements e0 .. e0+ne-1,

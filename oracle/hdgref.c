@@ -583,6 +583,14 @@ int hdgref_condense(int n, int f, const double *E, double *SK, double *gK, doubl
     return info;
 }
 
+/* Factor once, solve many times (the additive-Schwarz blocks inside GMRES):
+ * the same LU with partial pivoting as above, exposed in two calls. */
+int hdgref_lu_factor(int n, double *a, int *piv) { return lu_factor(n, a, n, piv); }
+void hdgref_lu_solve(int n, const double *a, const int *piv, double *b, int nrhs)
+{
+    lu_solve(n, a, n, piv, b, n, nrhs);
+}
+
 /* Dense LU solve of a general system (used for the additive-Schwarz blocks and
  * the brute-force check): solves a x = b in place for nrhs columns. */
 int hdgref_dense_solve(int n, double *a, double *b, int nrhs)

@@ -58,6 +58,10 @@ def lib():
             L.hdgref_condense.restype = ctypes.c_int
             L.hdgref_dense_solve.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
             L.hdgref_dense_solve.restype = ctypes.c_int
+            L.hdgref_lu_factor.argtypes = [ctypes.c_int, _dp, _ip]
+            L.hdgref_lu_factor.restype = ctypes.c_int
+            L.hdgref_lu_solve.argtypes = [ctypes.c_int, _dp, _ip, _dp, ctypes.c_int]
+            L.hdgref_lu_solve.restype = None
             L.hdgref_gauss.argtypes = [ctypes.c_int, _dp, _dp]
             L.hdgref_gll.argtypes = [ctypes.c_int, _dp]
             L.hdgref_point_flux.argtypes = [_dp, _dp, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
@@ -187,6 +191,24 @@ def dense_solve(A, b):
     return bb.reshape(b.shape)
 
 
+class LU:
+    """LU factors with partial pivoting (the oracle's own code) of a dense
+    matrix, kept for repeated solves."""
+
+    def __init__(self, A):
+        self.n = A.shape[0]
+        self.a = np.asfortranarray(A, dtype=np.float64).copy(order="F")
+        self.piv = np.zeros(self.n, dtype=np.int32)
+        info = lib().hdgref_lu_factor(self.n, self.a.ctypes.data_as(_dp), self.piv.ctypes.data_as(_ip))
+        assert info == 0, info
+
+    def solve(self, b):
+        bb = np.asfortranarray(b.reshape(b.shape[0], -1), dtype=np.float64).copy(order="F")
+        lib().hdgref_lu_solve(self.n, self.a.ctypes.data_as(_dp), self.piv.ctypes.data_as(_ip),
+                              bb.ctypes.data_as(_dp), bb.shape[1])
+        return bb.reshape(b.shape)
+
+
 def element_systems(wl, elems=None, threads=None):
     sizes = Sizes(wl.mesh)
     elems = range(wl.mesh.n_elem) if elems is None else elems
@@ -257,58 +279,79 @@ class TraceSystem:
             rows.append(np.concatenate([self.blocks[(int(Fa), int(Fb))] for Fb in faces], axis=1))
         return np.concatenate(rows, axis=0)
 
+    def asm_factor(self, threads=None):
+        """LU factors of every S_r (kept: GMRES applies M^{-1} once per iteration)."""
+        if self.asm_inv is None:
+            nthr = threads or min(16, os.cpu_count() or 1)
+            with ThreadPoolExecutor(max_workers=nthr) as ex:
+                self.asm_inv = list(ex.map(lambda r: LU(self.patch_matrix(r)), range(self.wl.mesh.n_elem)))
+        return self.asm_inv
+
     def asm_apply(self, y):
         """z = sum_r R_r^T S_r^{-1} R_r y (plain additive, no coarse space)."""
         z = np.zeros(self.N)
+        fac = self.asm_factor()
         for r in range(self.wl.mesh.n_elem):
             idx = self.patch_index(r)
-            z_loc = dense_solve(self.patch_matrix(r), y[idx])
-            np.add.at(z, idx, z_loc)
+            np.add.at(z, idx, fac[r].solve(y[idx]))
         return z
 
 
-def gmres(ts: TraceSystem, g, m, tol=0.0):
-    """Left-preconditioned GMRES(m), x0 = 0, modified Gram-Schmidt Arnoldi and
-    Givens rotations; returns (x, residual history of ||M^{-1}(g - S x_j)||)."""
-    r0 = ts.asm_apply(g)
-    beta = np.linalg.norm(r0)
+def gmres(ts: TraceSystem, g, m, tol=0.0, x0=None, restarts=1):
+    """Restarted, left-preconditioned GMRES(m) (section 3.2): each cycle
+    minimises ||M^{-1}(g - S x)||_2 over x0 + K_m(M^{-1}S, M^{-1}(g - S x0)) by
+    modified Gram-Schmidt Arnoldi, Givens rotations and back substitution; up
+    to `restarts` cycles, stopping once the preconditioned residual is at most
+    tol times the initial one.  x0 = 0 unless given.  Returns (x, history of
+    ||M^{-1}(g - S x_j)|| over all iterations)."""
     N = g.shape[0]
-    V = np.zeros((m + 1, N))
-    H = np.zeros((m + 1, m))
-    cs, sn = np.zeros(m), np.zeros(m)
-    gam = np.zeros(m + 1)
-    gam[0] = beta
-    hist = [beta]
-    if beta == 0.0:
-        return np.zeros(N), np.array(hist)
-    V[0] = r0 / beta
-    k = 0
-    for j in range(m):
-        w = ts.asm_apply(ts.matvec(V[j]))
-        for i in range(j + 1):
-            H[i, j] = np.dot(w, V[i])
-            w = w - H[i, j] * V[i]
-        H[j + 1, j] = np.linalg.norm(w)
-        if H[j + 1, j] != 0.0:
-            V[j + 1] = w / H[j + 1, j]
-        for i in range(j):
-            t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
-            H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
-            H[i, j] = t
-        den = np.hypot(H[j, j], H[j + 1, j])
-        cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
-        H[j, j] = den
-        H[j + 1, j] = 0.0
-        gam[j + 1] = -sn[j] * gam[j]
-        gam[j] = cs[j] * gam[j]
-        hist.append(abs(gam[j + 1]))
-        k = j + 1
-        if tol > 0.0 and abs(gam[j + 1]) <= tol * beta:
+    x = np.zeros(N) if x0 is None else np.array(x0, dtype=np.float64)
+    hist = []
+    beta0 = None
+    for cycle in range(restarts):
+        r0 = ts.asm_apply(g - ts.matvec(x)) if (x0 is not None or cycle > 0) else ts.asm_apply(g)
+        beta = np.linalg.norm(r0)
+        if beta0 is None:
+            beta0 = beta
+            hist.append(beta)
+        if beta == 0.0 or (tol > 0.0 and cycle > 0 and beta <= tol * beta0):
             break
-    y = np.zeros(k)
-    for i in range(k - 1, -1, -1):
-        y[i] = (gam[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
-    return V[:k].T @ y, np.array(hist)
+        V = np.zeros((m + 1, N))
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        gam = np.zeros(m + 1)
+        gam[0] = beta
+        V[0] = r0 / beta
+        k = 0
+        for j in range(m):
+            w = ts.asm_apply(ts.matvec(V[j]))
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            gam[j + 1] = -sn[j] * gam[j]
+            gam[j] = cs[j] * gam[j]
+            hist.append(abs(gam[j + 1]))
+            k = j + 1
+            if tol > 0.0 and abs(gam[j + 1]) <= tol * beta0:
+                break
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (gam[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+        x = x + V[:k].T @ y
+        if tol > 0.0 and hist[-1] <= tol * beta0:
+            break
+    return x, np.array(hist)
 
 
 def recover(wl, sizes, e, X, dUhat):

@@ -514,6 +514,11 @@ int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, siz
             if (ne < 1 || ne > 200) return HDG_ERR_INVALID_ARGUMENT;
             *bytes = hdg::gmres_work_bytes(ctx, ne);
             return HDG_OK;
+        case 5:
+            if (ne < 1 || ne > HDG_RB_MAX) return HDG_ERR_INVALID_ARGUMENT;
+            *bytes = hdg::rb_work_bytes(ctx, ne);
+            return HDG_OK;
+        case 6: *bytes = hdg::resid_work_bytes(ctx); return HDG_OK;
         default: return HDG_ERR_INVALID_ARGUMENT;
     }
 }
@@ -585,7 +590,69 @@ int hdg_gmres(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, con
         (prec != HDG_FP64 && prec != HDG_MIXED))
         return HDG_ERR_INVALID_ARGUMENT;
     if (work_bytes < hdg::gmres_work_bytes(ctx, m) || !work) return HDG_ERR_WORKSPACE;
-    return dev_status(hdg::launch_gmres(ctx, prec, S_bsr, Sinv, g, m, dUhat, res_hist, work, (hipStream_t)stream));
+    return dev_status(hdg::launch_gmres(ctx, prec, S_bsr, Sinv, g, nullptr, m, dUhat, res_hist, work,
+                                        (hipStream_t)stream));
+}
+
+int hdg_gmres_x0(hdg_ctx *ctx, int prec, const double *S_bsr, const void *Sinv, const double *g, const double *x0,
+                 int m, double *dUhat, double *res_hist, void *work, size_t work_bytes, void *stream) {
+    if (!ctx || !S_bsr || !Sinv || !g || !x0 || !dUhat || !res_hist || m < 1 || m > 200 ||
+        (prec != HDG_FP64 && prec != HDG_MIXED))
+        return HDG_ERR_INVALID_ARGUMENT;
+    if (work_bytes < hdg::gmres_work_bytes(ctx, m) || !work) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_gmres(ctx, prec, S_bsr, Sinv, g, x0, m, dUhat, res_hist, work,
+                                        (hipStream_t)stream));
+}
+
+int hdg_rb_guess(hdg_ctx *ctx, int nb, const double *W, const double *Z, const double *g, double *x0, void *work,
+                 size_t work_bytes, void *stream) {
+    if (!ctx || !g || !x0 || nb < 0 || nb > HDG_RB_MAX || (nb > 0 && (!W || !Z))) return HDG_ERR_INVALID_ARGUMENT;
+    if (nb > 0 && (!work || work_bytes < hdg::rb_work_bytes(ctx, nb))) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_rb_guess(ctx, nb, W, Z, g, x0, work, (hipStream_t)stream));
+}
+
+int hdg_rb_insert(hdg_ctx *ctx, const double *S_bsr, const double *w_new, int nb_max, int *count, int *head,
+                  double *W, double *Z, void *stream) {
+    if (!ctx || !S_bsr || !w_new || !count || !head || !W || !Z || nb_max < 1 || nb_max > HDG_RB_MAX)
+        return HDG_ERR_INVALID_ARGUMENT;
+    if (*count < 0 || *count > nb_max || *head < 0 || *head >= nb_max) return HDG_ERR_INVALID_ARGUMENT;
+    const int rc = hdg::launch_rb_insert(ctx, S_bsr, w_new, *head, W, Z, (hipStream_t)stream);
+    if (rc) return HDG_ERR_DEVICE;
+    *head = (*head + 1) % nb_max;
+    *count = std::min(*count + 1, nb_max);
+    return HDG_OK;
+}
+
+int hdg_state_update(hdg_ctx *ctx, double alpha, const double *dQU, const double *dUhat, double *Q, double *U,
+                     double *Uhat, void *stream) {
+    if (!ctx || !dQU || !dUhat || !Q || !U || !Uhat || !std::isfinite(alpha)) return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_state_update(ctx, alpha, dQU, dUhat, Q, U, Uhat, (hipStream_t)stream));
+}
+
+int hdg_state_admissible(hdg_ctx *ctx, double alpha, const double *U, const double *dQU, int *flag, void *stream) {
+    if (!ctx || !U || !dQU || !flag || !std::isfinite(alpha)) return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_admissible(ctx, alpha, U, dQU, flag, (hipStream_t)stream));
+}
+
+int hdg_lincomb(hdg_ctx *ctx, int k, const double *const *v, const double *coef, double *out, int64_t n,
+                void *stream) {
+    if (!ctx || k < 1 || k > 8 || !v || !coef || !out || n < 0) return HDG_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < k; ++i)
+        if (!v[i] || !std::isfinite(coef[i])) return HDG_ERR_INVALID_ARGUMENT;
+    if (n == 0) return HDG_OK;
+    return dev_status(hdg::launch_lincomb(k, v, coef, out, n, (hipStream_t)stream));
+}
+
+int hdg_residual_gather(hdg_ctx *ctx, int e0, int ne, const double *E, void *work, size_t work_bytes, void *stream) {
+    if (!chunk_ok(ctx, e0, ne) || !E) return HDG_ERR_INVALID_ARGUMENT;
+    if (!work || work_bytes < hdg::resid_work_bytes(ctx)) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_resid_elem(ctx, e0, ne, E, work, (hipStream_t)stream));
+}
+
+int hdg_residual_norm(hdg_ctx *ctx, void *work, size_t work_bytes, double *norms, void *stream) {
+    if (!ctx || !norms) return HDG_ERR_INVALID_ARGUMENT;
+    if (!work || work_bytes < hdg::resid_work_bytes(ctx)) return HDG_ERR_WORKSPACE;
+    return dev_status(hdg::launch_resid_norm(ctx, work, norms, (hipStream_t)stream));
 }
 
 int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E, const double *dUhat,

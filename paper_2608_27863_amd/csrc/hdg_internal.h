@@ -129,7 +129,20 @@ int asm_scratch_init(int device);
 int launch_asm_apply_noalloc(const hdg_ctx *ctx, int prec, const void *Sinv, const double *r, double *z,
                              hipStream_t s);
 int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv, const double *g,
-                 int m, double *x, double *hist, void *work, hipStream_t s);
+                 const double *x0, int m, double *x, double *hist, void *work, hipStream_t s);
+size_t rb_work_bytes(const hdg_ctx *ctx, int nb_max);
+int launch_rb_guess(const hdg_ctx *ctx, int nb, const double *W, const double *Z, const double *g, double *x0,
+                    void *work, hipStream_t s);
+int launch_rb_insert(const hdg_ctx *ctx, const double *S, const double *w_new, int slot, double *W, double *Z,
+                     hipStream_t s);
+int launch_state_update(const hdg_ctx *ctx, double alpha, const double *dQU, const double *dUhat, double *Q,
+                        double *U, double *Uhat, hipStream_t s);
+int launch_lincomb(int k, const double *const *v, const double *c, double *out, int64_t n, hipStream_t s);
+size_t resid_work_bytes(const hdg_ctx *ctx);
+int launch_resid_elem(const hdg_ctx *ctx, int e0, int ne, const double *E, void *work, hipStream_t s);
+int launch_resid_norm(const hdg_ctx *ctx, void *work, double *out, hipStream_t s);
+int launch_admissible(const hdg_ctx *ctx, double alpha, const double *U, const double *dQU, int *flag,
+                      hipStream_t s);
 size_t gmres_work_bytes(const hdg_ctx *ctx, int m);
 int launch_recover(const hdg_ctx *ctx, int prec, int e0, int ne, const double *E,
                    const double *dUhat, double *dQU, hipStream_t s);

@@ -334,14 +334,189 @@ __global__ void k_upper_solve(const double *__restrict__ H, int m, const double 
     }
 }
 
-// x = sum_v y[v] V[v]
+// x = x0 + sum_v y[v] V[v]  (x0 = NULL: 0; x may alias x0)
 __global__ void __launch_bounds__(256) k_combine(const double *__restrict__ V, int nv, int64_t ldv,
-                                                 const double *__restrict__ y, double *__restrict__ x, int64_t N) {
+                                                 const double *__restrict__ y, const double *x0, double *x,
+                                                 int64_t N) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
+        double s = x0 ? x0[i] : 0.0;
         for (int v = 0; v < nv; ++v) s += y[v] * V[v * ldv + i];
         x[i] = s;
     }
+}
+
+// t = g - t  (the initial residual g - S x0, with S x0 already in t)
+__global__ void __launch_bounds__(256) k_rsub(const double *__restrict__ g, double *__restrict__ t, int64_t N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        t[i] = g[i] - t[i];
+}
+
+__global__ void __launch_bounds__(256) k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------ reduced basis (eq. rb-min)
+// Column j of the QR factorisation of Z by classical Gram-Schmidt applied
+// twice: after the two projections, q (in Qz[j]) has norm^2 *nrm_sq and the
+// column before them *z_sq.  A column whose part orthogonal to the previous
+// ones is below kRbDrop of its norm is dependent on them: it gets R_jj = 0 and
+// q = 0, and its coefficient is then 0 (the kept columns span the same space).
+constexpr double kRbDrop = 1e-12;
+__global__ void k_rb_diag(const double *__restrict__ nrm_sq, const double *__restrict__ z_sq, double *__restrict__ Rjj) {
+    const double nr = sqrt(*nrm_sq), nz = sqrt(*z_sq);
+    *Rjj = (nr > kRbDrop * nz && nr > 0.0) ? nr : 0.0;
+}
+// dst = src / *d (0 if *d is 0)
+__global__ void __launch_bounds__(256) k_scale_by(const double *__restrict__ src, const double *__restrict__ d,
+                                                  double *__restrict__ dst, int64_t N) {
+    const double s = (*d != 0.0) ? 1.0 / *d : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] * s;
+}
+
+// ------------------------------------------------------------ Newton update
+// W += alpha dW (eq. newton-update): Q, U from the packed interior increment
+// dQU ([e][20][node]: 15 gradient fields, then 5 conserved), Uhat from dUhat.
+__global__ void __launch_bounds__(256) k_state_update(DevMesh dm, double alpha, const double *__restrict__ dQU,
+                                                      const double *__restrict__ dUhat, double *__restrict__ Q,
+                                                      double *__restrict__ U, double *__restrict__ Uhat) {
+    const int e = blockIdx.x;
+    if (e < dm.n_elem) {
+        const int p = dm.elem_p[e], Np = (p + 1) * (p + 1) * (p + 1);
+        const int64_t o = dm.node_off[e];
+        const double *d = dQU + 20 * o;
+        for (int i = threadIdx.x; i < 15 * Np; i += blockDim.x) Q[15 * o + i] += alpha * d[i];
+        for (int i = threadIdx.x; i < 5 * Np; i += blockDim.x) U[5 * o + i] += alpha * d[15 * Np + i];
+    }
+    // the trace: faces spread over the same blocks
+    const int64_t N = dm.face_off[dm.n_face];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        Uhat[i] += alpha * dUhat[i];
+}
+
+// out = sum_k coef[k] v_k over n values (k < 8): the DIRK combinations of
+// eqs. dirk-stage and dirk-update
+struct LinComb {
+    const double *v[8];
+    double c[8];
+    int k;
+};
+__global__ void __launch_bounds__(256) k_lincomb(LinComb lc, double *__restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < lc.k; ++k) s += lc.c[k] * lc.v[k][i];
+        out[i] = s;
+    }
+}
+
+// Nonlinear residual norm (eq. nonlinear-residual), from element systems just
+// written by the residual kernels: per element, the sums of squares of R_q and
+// R_u into part[2 e], [2 e + 1], and the element-side trace residual R_uh^K
+// copied to ruh_loc (element-local trace order) for the face assembly.
+__global__ void __launch_bounds__(256) k_resid_elem(DevMesh dm, int e0, const double *__restrict__ Ebase,
+                                                    double *__restrict__ part, double *__restrict__ ruh_loc) {
+    const int e = e0 + blockIdx.x;
+    const int p = dm.elem_p[e], Np = (p + 1) * (p + 1) * (p + 1), n = 20 * Np;
+    const int f = dm.toff[7 * e + 6];
+    const int64_t ld = e_ld(n, f);
+    const double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    __shared__ double red[2][256];
+    double sq = 0.0, su = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double r = E[(int64_t)i * ld + n + f];
+        if (i < 15 * Np) sq += r * r;
+        else su += r * r;
+    }
+    for (int a = threadIdx.x; a < f; a += blockDim.x) ruh_loc[dm.tloc_off[e] + a] = E[(int64_t)(n + a) * ld + n + f];
+    red[0][threadIdx.x] = sq;
+    red[1][threadIdx.x] = su;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * e] = red[0][0];
+        part[2 * e + 1] = red[1][0];
+    }
+}
+
+// Per face: the assembled trace residual R_uh[F] = sum over the face's
+// elements of R_uh^K (fixed order), its sum of squares into fpart[F].
+__global__ void __launch_bounds__(128) k_resid_face(DevMesh dm, const double *__restrict__ ruh_loc,
+                                                    double *__restrict__ fpart) {
+    const int F = blockIdx.x;
+    const int bF = (int)(dm.face_off[F + 1] - dm.face_off[F]);
+    const int s0 = dm.face_src_ptr[F], s1 = dm.face_src_ptr[F + 1];
+    __shared__ double red[128];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < bF; i += blockDim.x) {
+        double v = 0.0;
+        for (int s = s0; s < s1; ++s) {
+            const int e = dm.face_src[2 * s], a = dm.face_src[2 * s + 1];
+            v += ruh_loc[dm.tloc_off[e] + dm.toff[7 * e + a] + i];
+        }
+        acc += v * v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 64; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) fpart[F] = red[0];
+}
+
+// out[0..2] = ||R_q||, ||R_u||, ||R_uh|| from the per-element and per-face
+// partial sums (one block, fixed-shape tree: deterministic)
+__global__ void __launch_bounds__(256) k_resid_final(const double *__restrict__ part, int ne,
+                                                     const double *__restrict__ fpart, int nf, double *__restrict__ out) {
+    __shared__ double red[3][256];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        a += part[2 * e];
+        b += part[2 * e + 1];
+    }
+    for (int F = threadIdx.x; F < nf; F += blockDim.x) c += fpart[F];
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    red[2][threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) out[q] = sqrt(red[q][0]);
+}
+
+__global__ void k_zero_flag(int *flag) { flag[0] = 0; }
+
+// Admissibility of W + alpha dW at the nodes: flag[0] = 1 if any node would
+// have non-positive density or pressure (or a non-finite value), else
+// untouched (k_zero_flag clears it first).
+__global__ void __launch_bounds__(256) k_admissible(DevMesh dm, double alpha, double gamma, const double *__restrict__ U,
+                                                    const double *__restrict__ dQU, int *__restrict__ flag) {
+    const int e = blockIdx.x;
+    const int p = dm.elem_p[e], Np = (p + 1) * (p + 1) * (p + 1);
+    const int64_t o = dm.node_off[e];
+    const double *u = U + 5 * o;
+    const double *d = dQU + 20 * o + 15 * Np;
+    bool bad = false;
+    for (int i = threadIdx.x; i < Np; i += blockDim.x) {
+        double w[5];
+        for (int c = 0; c < 5; ++c) w[c] = u[c * Np + i] + alpha * d[c * Np + i];
+        const double rho = w[0];
+        const double ke = 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho;
+        const double pr = (gamma - 1.0) * (w[4] - ke);
+        if (!(rho > 0.0) || !(pr > 0.0) || !isfinite(pr)) bad = true;
+    }
+    if (bad) flag[0] = 1;
 }
 
 // ------------------------------------------------------------------ recovery
@@ -563,8 +738,8 @@ size_t gmres_work_bytes(const hdg_ctx *ctx, int m) {
     return gmres_layout(ctx, m, off);
 }
 
-int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv, const double *g, int m, double *x,
-                 double *hist, void *work, hipStream_t s) {
+int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv, const double *g, const double *x0,
+                 int m, double *x, double *hist, void *work, hipStream_t s) {
     size_t off[12];
     gmres_layout(ctx, m, off);
     double *W = (double *)work;
@@ -575,8 +750,14 @@ int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv
     const int stride = m + 2;
     const int gN = grid_for(N);
     int err;
-    // r0 = M^{-1} g, beta = ||r0||, v0 = r0 / beta
-    if ((err = launch_asm_apply(ctx, prec, Sinv, g, w, zloc, s))) return err;
+    // r0 = M^{-1} (g - S x0), beta = ||r0||, v0 = r0 / beta
+    if (x0) {
+        if ((err = launch_matvec(ctx, S, x0, t, s))) return err;
+        hipLaunchKernelGGL(k_rsub, dim3(gN), dim3(256), 0, s, g, t, N);
+        if ((err = launch_asm_apply(ctx, prec, Sinv, t, w, zloc, s))) return err;
+    } else {
+        if ((err = launch_asm_apply(ctx, prec, Sinv, g, w, zloc, s))) return err;
+    }
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)w, 1, (int64_t)0,
                        (const double *)w, N, partial, stride);
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, (const double *)partial, kDotBlocks, stride, 1, scal, 0);
@@ -607,7 +788,137 @@ int launch_gmres(const hdg_ctx *ctx, int prec, const double *S, const void *Sinv
         hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, H, m, j, (const double *)scal, cs, sn, gam, hist);
     }
     hipLaunchKernelGGL(k_upper_solve, dim3(1), dim3(1), 0, s, (const double *)H, m, (const double *)gam, y);
-    hipLaunchKernelGGL(k_combine, dim3(gN), dim3(256), 0, s, (const double *)V, m, N, (const double *)y, x, N);
+    hipLaunchKernelGGL(k_combine, dim3(gN), dim3(256), 0, s, (const double *)V, m, N, (const double *)y, x0, x, N);
+    return (int)hipGetLastError();
+}
+
+// Reduced-basis guess workspace (doubles): Qz[nb N] | R[(nb+1) nb] | qg[nb] | c[nb] |
+//                                         partial[kDotBlocks (nb+2)] | scal[8]
+static size_t rb_layout(const hdg_ctx *ctx, int nb, size_t *off) {
+    const size_t N = (size_t)ctx->face_off[ctx->n_face];
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t at = o; o += (n + 31) / 32 * 32; return at; };
+    off[0] = take((size_t)nb * N);
+    off[1] = take((size_t)(nb + 1) * nb);
+    off[2] = take(nb);
+    off[3] = take(nb);
+    off[4] = take((size_t)kDotBlocks * (nb + 2));
+    off[5] = take(8);
+    return o * sizeof(double);
+}
+
+size_t rb_work_bytes(const hdg_ctx *ctx, int nb_max) {
+    size_t off[6];
+    return rb_layout(ctx, nb_max, off);
+}
+
+// x0 = W c, c = argmin ||g - Z c||_2 over the `nb` stored columns
+// (eq. rb-min): CGS2 QR of Z, c = R^{-1} Q^T g (dependent columns get c = 0).
+int launch_rb_guess(const hdg_ctx *ctx, int nb, const double *Wb, const double *Zb, const double *g, double *x0,
+                    void *work, hipStream_t s) {
+    const int64_t N = ctx->face_off[ctx->n_face];
+    const int gN = grid_for(N);
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_combine, dim3(gN), dim3(256), 0, s, Wb, 0, N, (const double *)nullptr,
+                           (const double *)nullptr, x0, N);
+        return (int)hipGetLastError();
+    }
+    size_t off[6];
+    rb_layout(ctx, nb, off);
+    double *Wk = (double *)work;
+    double *Qz = Wk + off[0], *R = Wk + off[1], *qg = Wk + off[2], *c = Wk + off[3];
+    double *partial = Wk + off[4], *scal = Wk + off[5];
+    const int ldr = nb + 1, stride = nb + 2;
+    for (int j = 0; j < nb; ++j) {
+        double *q = Qz + (int64_t)j * N;
+        double *rj = R + (int64_t)j * ldr;
+        hipLaunchKernelGGL(k_copy, dim3(gN), dim3(256), 0, s, Zb + (int64_t)j * N, q, N);
+        // ||z_j||^2 -> scal[1]
+        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)q, 1, (int64_t)0,
+                           (const double *)q, N, partial, stride);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, (const double *)partial, kDotBlocks, stride, 1,
+                           scal + 1, 0);
+        if (j > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)Qz, j, N,
+                                   (const double *)q, N, partial, stride);
+                // pass 0 writes R[0..j-1, j]; pass 1 its correction (scal+2..), then adds it
+                hipLaunchKernelGGL(k_dot_final, dim3(j), dim3(256), 0, s, (const double *)partial, kDotBlocks, stride,
+                                   j, pass == 0 ? rj : c, 0);
+                hipLaunchKernelGGL(k_sub_multi, dim3(gN), dim3(256), 0, s, (const double *)Qz, j, N,
+                                   (const double *)(pass == 0 ? rj : c), q, N);
+                if (pass == 1)
+                    hipLaunchKernelGGL(k_dot_final, dim3(j), dim3(256), 0, s, (const double *)partial, kDotBlocks,
+                                       stride, j, rj, 1);
+            }
+        }
+        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)q, 1, (int64_t)0,
+                           (const double *)q, N, partial, stride);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, (const double *)partial, kDotBlocks, stride, 1,
+                           scal, 0);
+        hipLaunchKernelGGL(k_rb_diag, dim3(1), dim3(1), 0, s, (const double *)scal, (const double *)(scal + 1), rj + j);
+        hipLaunchKernelGGL(k_scale_by, dim3(gN), dim3(256), 0, s, (const double *)q, (const double *)(rj + j), q, N);
+    }
+    // qg = Q^T g, c = R^{-1} qg, x0 = W c
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, (const double *)Qz, nb, N, g, N, partial,
+                       stride);
+    hipLaunchKernelGGL(k_dot_final, dim3(nb), dim3(256), 0, s, (const double *)partial, kDotBlocks, stride, nb, qg, 0);
+    hipLaunchKernelGGL(k_upper_solve, dim3(1), dim3(1), 0, s, (const double *)R, nb, (const double *)qg, c);
+    hipLaunchKernelGGL(k_combine, dim3(gN), dim3(256), 0, s, Wb, nb, N, (const double *)c, (const double *)nullptr,
+                       x0, N);
+    return (int)hipGetLastError();
+}
+
+// W[:, slot] = w_new, Z[:, slot] = S w_new
+int launch_rb_insert(const hdg_ctx *ctx, const double *S, const double *w_new, int slot, double *Wb, double *Zb,
+                     hipStream_t s) {
+    const int64_t N = ctx->face_off[ctx->n_face];
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(N)), dim3(256), 0, s, w_new, Wb + (int64_t)slot * N, N);
+    return launch_matvec(ctx, S, w_new, Zb + (int64_t)slot * N, s);
+}
+
+int launch_state_update(const hdg_ctx *ctx, double alpha, const double *dQU, const double *dUhat, double *Q,
+                        double *U, double *Uhat, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_update, dim3(ctx->n_elem), dim3(256), 0, s, ctx->dm, alpha, dQU, dUhat, Q, U, Uhat);
+    return (int)hipGetLastError();
+}
+
+int launch_lincomb(int k, const double *const *v, const double *c, double *out, int64_t n, hipStream_t s) {
+    LinComb lc{};
+    lc.k = k;
+    for (int i = 0; i < k; ++i) {
+        lc.v[i] = v[i];
+        lc.c[i] = c[i];
+    }
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n)), dim3(256), 0, s, lc, out, n);
+    return (int)hipGetLastError();
+}
+
+size_t resid_work_bytes(const hdg_ctx *ctx) {
+    return sizeof(double) * ((size_t)2 * ctx->n_elem + (size_t)ctx->tloc_off[ctx->n_elem] + (size_t)ctx->n_face) + 256;
+}
+
+int launch_resid_elem(const hdg_ctx *ctx, int e0, int ne, const double *E, void *work, hipStream_t s) {
+    double *part = (double *)work;
+    double *ruh = part + 2 * (size_t)ctx->n_elem;
+    hipLaunchKernelGGL(k_resid_elem, dim3(ne), dim3(256), 0, s, ctx->dm, e0, E, part, ruh);
+    return (int)hipGetLastError();
+}
+
+int launch_resid_norm(const hdg_ctx *ctx, void *work, double *out, hipStream_t s) {
+    double *part = (double *)work;
+    double *ruh = part + 2 * (size_t)ctx->n_elem;
+    double *fpart = ruh + (size_t)ctx->tloc_off[ctx->n_elem];
+    hipLaunchKernelGGL(k_resid_face, dim3(ctx->n_face), dim3(128), 0, s, ctx->dm, (const double *)ruh, fpart);
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, (const double *)part, ctx->n_elem,
+                       (const double *)fpart, ctx->n_face, out);
+    return (int)hipGetLastError();
+}
+
+int launch_admissible(const hdg_ctx *ctx, double alpha, const double *U, const double *dQU, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, s, flag);
+    hipLaunchKernelGGL(k_admissible, dim3(ctx->n_elem), dim3(256), 0, s, ctx->dm, alpha, ctx->phys.gamma, U, dQU,
+                       flag);
     return (int)hipGetLastError();
 }
 

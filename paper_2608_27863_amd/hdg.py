@@ -26,7 +26,10 @@ EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_
            "hdg_workspace_size", "hdg_local_residual_jacobian", "hdg_condense", "hdg_assemble_trace",
            "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior",
            "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy",
-           "hdg_asm_block_apply_noalloc"]
+           "hdg_asm_block_apply_noalloc", "hdg_gmres_x0", "hdg_rb_guess", "hdg_rb_insert", "hdg_state_update",
+           "hdg_state_admissible", "hdg_lincomb", "hdg_residual_gather", "hdg_residual_norm"]
+
+RB_MAX = 32
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -91,6 +94,15 @@ def load_library(path: str = LIB_PATH):
     L.hdg_graph_destroy.argtypes = [_vp]
     L.hdg_graph_destroy.restype = None
     L.hdg_asm_block_apply_noalloc.argtypes = [_vp, _i, _vp, _vp, _vp, _vp]
+    L.hdg_gmres_x0.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_rb_guess.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_rb_insert.argtypes = [_vp, _vp, _vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _vp, _vp, _vp]
+    L.hdg_state_update.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.hdg_state_admissible.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+    L.hdg_lincomb.argtypes = [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_int64,
+                              _vp]
+    L.hdg_residual_gather.argtypes = [_vp, _i, _i, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_residual_norm.argtypes = [_vp, _vp, ctypes.c_size_t, _vp, _vp]
     for name in EXPORTS:
         if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length", "hdg_graph_destroy"):
             getattr(L, name).restype = _i
@@ -266,6 +278,77 @@ class Context:
             self.h, prec, _ptr(Sinv, self._sinv_dtype(prec), int(self.layout["asm_off"][-1]), "Sinv"),
             _ptr(r, torch.float64, self.N_uh, "r"), _ptr(z, torch.float64, self.N_uh, "z"), _stream(stream))
         _check(rc, "hdg_asm_block_apply_noalloc")
+
+    # ------------------------------------------------- solver-loop calls
+    def hdg_gmres_x0(self, prec, S, Sinv, g, x0, m, dUhat, res_hist, work, stream=None):
+        import torch
+        f64 = torch.float64
+        rc = self.L.hdg_gmres_x0(self.h, prec, _ptr(S, f64, int(self.layout["bsr_val_off"][-1]), "S"),
+                                 _ptr(Sinv, self._sinv_dtype(prec), int(self.layout["asm_off"][-1]), "Sinv"),
+                                 _ptr(g, f64, self.N_uh, "g"), _ptr(x0, f64, self.N_uh, "x0"), int(m),
+                                 _ptr(dUhat, f64, self.N_uh, "dUhat"), _ptr(res_hist, f64, m + 1, "res_hist"),
+                                 _ptr(work, None, None, "work"), work.numel() * work.element_size(), _stream(stream))
+        _check(rc, "hdg_gmres_x0")
+
+    def hdg_rb_guess(self, nb, W, Z, g, x0, work, stream=None):
+        import torch
+        f64 = torch.float64
+        rc = self.L.hdg_rb_guess(self.h, int(nb), _ptr(W, f64, nb * self.N_uh, "W") if nb else None,
+                                 _ptr(Z, f64, nb * self.N_uh, "Z") if nb else None, _ptr(g, f64, self.N_uh, "g"),
+                                 _ptr(x0, f64, self.N_uh, "x0"), _ptr(work, None, None, "work") if work is not None
+                                 else None, 0 if work is None else work.numel() * work.element_size(),
+                                 _stream(stream))
+        _check(rc, "hdg_rb_guess")
+
+    def hdg_rb_insert(self, S, w_new, nb_max, count, head, W, Z, stream=None):
+        """Returns the new (count, head)."""
+        import torch
+        f64 = torch.float64
+        c, h = _i(count), _i(head)
+        rc = self.L.hdg_rb_insert(self.h, _ptr(S, f64, int(self.layout["bsr_val_off"][-1]), "S"),
+                                  _ptr(w_new, f64, self.N_uh, "w_new"), int(nb_max), ctypes.byref(c), ctypes.byref(h),
+                                  _ptr(W, f64, nb_max * self.N_uh, "W"), _ptr(Z, f64, nb_max * self.N_uh, "Z"),
+                                  _stream(stream))
+        _check(rc, "hdg_rb_insert")
+        return c.value, h.value
+
+    def hdg_state_update(self, alpha, dQU, dUhat, Q, U, Uhat, stream=None):
+        import torch
+        f64 = torch.float64
+        nn = int(self.layout["node_off"][-1])
+        rc = self.L.hdg_state_update(self.h, float(alpha), _ptr(dQU, f64, 20 * nn, "dQU"),
+                                     _ptr(dUhat, f64, self.N_uh, "dUhat"), _ptr(Q, f64, 15 * nn, "Q"),
+                                     _ptr(U, f64, 5 * nn, "U"), _ptr(Uhat, f64, self.N_uh, "Uhat"), _stream(stream))
+        _check(rc, "hdg_state_update")
+
+    def hdg_state_admissible(self, alpha, U, dQU, flag, stream=None):
+        import torch
+        nn = int(self.layout["node_off"][-1])
+        rc = self.L.hdg_state_admissible(self.h, float(alpha), _ptr(U, torch.float64, 5 * nn, "U"),
+                                         _ptr(dQU, torch.float64, 20 * nn, "dQU"), _ptr(flag, torch.int32, 1, "flag"),
+                                         _stream(stream))
+        _check(rc, "hdg_state_admissible")
+
+    def hdg_lincomb(self, vecs, coefs, out, stream=None):
+        import torch
+        n = out.numel()
+        vs = (_vp * len(vecs))(*[_ptr(v, torch.float64, n, "v") for v in vecs])
+        cs = (ctypes.c_double * len(coefs))(*[float(c) for c in coefs])
+        rc = self.L.hdg_lincomb(self.h, len(vecs), vs, cs, _ptr(out, torch.float64, n, "out"), n, _stream(stream))
+        _check(rc, "hdg_lincomb")
+
+    def hdg_residual_gather(self, e0, ne, E, work, stream=None):
+        import torch
+        rc = self.L.hdg_residual_gather(self.h, e0, ne, _ptr(E, torch.float64, self.e_size(e0, ne), "E"),
+                                        _ptr(work, None, None, "work"), work.numel() * work.element_size(),
+                                        _stream(stream))
+        _check(rc, "hdg_residual_gather")
+
+    def hdg_residual_norm(self, work, norms, stream=None):
+        import torch
+        rc = self.L.hdg_residual_norm(self.h, _ptr(work, None, None, "work"), work.numel() * work.element_size(),
+                                      _ptr(norms, torch.float64, 3, "norms"), _stream(stream))
+        _check(rc, "hdg_residual_norm")
 
     # ------------------------------------------------------- whole step
     def newton_args(self, st):

@@ -132,3 +132,135 @@ class NewtonStep:
         graph = self.ctx.hdg_graph_capture_newton(self._args, s)
         torch.cuda.synchronize()
         return graph
+
+
+class NewtonSolver:
+    """Newton's method for one DIRK stage (sections 2.4-3.4) on the buffers of a
+    NewtonStep: the state (Q, U, Uhat) is updated in place, the lagged state
+    of the mass term is the step's Un.  Each iteration evaluates the element
+    residuals and Jacobians, gathers the residual norm (eq. nonlinear-residual),
+    stops once it is at most max(atol, tol * the first one), else condenses,
+    assembles, sets up the Schwarz blocks, takes the reduced-basis guess
+    (eq. rb-min; window of rb_max accepted corrections, 0 = no guess), runs
+    GMRES from it, inserts the accepted correction into the window, recovers
+    the interior correction and updates the state with the largest
+    alpha in {1, 1/2, ..., 2^-10} that keeps density and pressure positive
+    (eq. newton-update).  The host reads three norms and a flag per iteration;
+    all arithmetic runs in libhdg's kernels."""
+
+    def __init__(self, step, rb_max=0, tol=1e-10, atol=1e-11, maxit=8):
+        import torch
+        self.st = step
+        ctx = step.ctx
+        self.tol, self.atol, self.maxit = tol, atol, maxit
+        dev = step.E.device
+        self.rwork = torch.empty(ctx.workspace_size(6), dtype=torch.uint8, device=dev)
+        self.norms = torch.zeros(3, dtype=torch.float64, device=dev)
+        self.flag = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.rb_max = int(rb_max)
+        self.count = self.head = 0
+        if self.rb_max:
+            if not 1 <= self.rb_max <= 32:
+                raise ValueError("rb_max must be in 0..32")
+            self.W = torch.zeros(self.rb_max * ctx.N_uh, dtype=torch.float64, device=dev)
+            self.Z = torch.zeros_like(self.W)
+            self.x0 = torch.zeros(ctx.N_uh, dtype=torch.float64, device=dev)
+            self.rb_work = torch.empty(ctx.workspace_size(5, 0, 0, self.rb_max), dtype=torch.uint8, device=dev)
+
+    def residual(self, stream=None):
+        """Element systems at the current state and (||R_q||, ||R_u||, ||R_uh||)."""
+        st, ctx = self.st, self.st.ctx
+        for e0, n in st.chunks:
+            ctx.hdg_local_residual_jacobian(e0, n, st.Q, st.U, st.Un, st.Uhat, st.nu,
+                                            st.Ub if st.wl.mesh.face_bc.any() else None, st.E_chunk(e0, n),
+                                            st.qp_work, stream)
+            ctx.hdg_residual_gather(e0, n, st.E_chunk(e0, n), self.rwork, stream)
+        ctx.hdg_residual_norm(self.rwork, self.norms, stream)
+        return tuple(float(v) for v in self.norms.cpu())
+
+    def solve(self, stream=None):
+        """Returns the history [(||R_q||, ||R_u||, ||R_uh||, alpha, GMRES history), ...]."""
+        import math
+        st, ctx = self.st, self.st.ctx
+        hist, f0 = [], None
+        for it in range(self.maxit + 1):
+            nr = self.residual(stream)
+            fn = math.sqrt(sum(v * v for v in nr))
+            f0 = fn if f0 is None else f0
+            if fn <= max(self.atol, self.tol * f0) or it == self.maxit:
+                hist.append((*nr, None, None))
+                break
+            st.condense(stream)
+            st.assemble(stream)
+            st.asm_setup(stream)
+            if self.rb_max and self.count:
+                ctx.hdg_rb_guess(self.count, self.W, self.Z, st.g, self.x0, self.rb_work, stream)
+                ctx.hdg_gmres_x0(st.asm_prec, st.S, st.Sinv, st.g, self.x0, st.m, st.dUhat, st.hist, st.gm_work,
+                                 stream)
+            else:
+                st.gmres(stream)
+            if self.rb_max:
+                self.count, self.head = ctx.hdg_rb_insert(st.S, st.dUhat, self.rb_max, self.count, self.head,
+                                                          self.W, self.Z, stream)
+            st.recover(stream)
+            alpha = 1.0
+            while True:
+                ctx.hdg_state_admissible(alpha, st.U, st.dQU, self.flag, stream)
+                if int(self.flag.cpu()[0]) == 0 or alpha <= 2.0 ** -10:
+                    break
+                alpha *= 0.5
+            ctx.hdg_state_update(alpha, st.dQU, st.dUhat, st.Q, st.U, st.Uhat, stream)
+            hist.append((*nr, alpha, st.hist.cpu().numpy().copy()))
+        return hist
+
+
+def alexander_dirk():
+    """Alexander's three-stage, third-order, L-stable DIRK: (A, b) with
+    a_ii = gamma, the root near 0.4359 of gamma^3 - 3 gamma^2 + 3 gamma / 2 - 1/6,
+    a_21 = (1 - gamma)/2, last row b = (-(6g^2 - 16g + 1)/4, (6g^2 - 20g + 5)/4, g);
+    and the coefficients d = A^{-1}, e = b^T d of eqs. dirk-stage, dirk-update."""
+    g = 0.4358
+    for _ in range(50):  # Newton on the cubic
+        g -= (g ** 3 - 3 * g ** 2 + 1.5 * g - 1.0 / 6.0) / (3 * g ** 2 - 6 * g + 1.5)
+    b = [-(6 * g * g - 16 * g + 1) / 4, (6 * g * g - 20 * g + 5) / 4, g]
+    A = [[g, 0.0, 0.0], [(1 - g) / 2, g, 0.0], list(b)]
+    # inverse of the lower-triangular A by forward substitution, column by column
+    d = [[0.0] * 3 for _ in range(3)]
+    for col in range(3):
+        for r in range(3):
+            s = (1.0 if r == col else 0.0) - sum(A[r][k] * d[k][col] for k in range(r))
+            d[r][col] = s / A[r][r]
+    e = [sum(b[i] * d[i][j] for i in range(3)) for j in range(3)]
+    return A, b, d, e
+
+
+class DirkStepper:
+    """One time step of the three-stage DIRK (eqs. dirk-stage, dirk-update) on a
+    NewtonSolver's buffers: stage i sets the lagged state
+    Un <- U^n - sum_{j<i} (d_ij / d_ii)(U^{n,j} - U^n) (so that the residual's
+    d_ii M (U - Un) is the stage's mass term) and solves from the previous
+    stage's state; then U <- (1 - sum_j e_j) U^n + sum_j e_j U^{n,j}, keeping Q
+    and Uhat of the last stage (the tableau is stiffly accurate: e = (0, 0, 1)).
+    The context's alpha must be d_ii."""
+
+    def __init__(self, solver):
+        import torch
+        self.solver = solver
+        st = solver.st
+        self.A, self.b, self.d, self.e = alexander_dirk()
+        if abs(st.wl.alpha - self.d[0][0]) > 1e-12 * self.d[0][0]:
+            raise ValueError("the context's alpha must equal d_ii = 1 / gamma of the tableau")
+        self.Un = torch.empty_like(st.U)
+        self.stages = [torch.empty_like(st.U) for _ in range(3)]
+
+    def step(self, stream=None):
+        st, ctx, d, e = self.solver.st, self.solver.st.ctx, self.d, self.e
+        ctx.hdg_lincomb([st.U], [1.0], self.Un, stream)
+        hists = []
+        for i in range(3):
+            coefs = [1.0 + sum(d[i][j] / d[i][i] for j in range(i))] + [-d[i][j] / d[i][i] for j in range(i)]
+            ctx.hdg_lincomb([self.Un] + self.stages[:i], coefs, st.Un, stream)
+            hists.append(self.solver.solve(stream))
+            ctx.hdg_lincomb([st.U], [1.0], self.stages[i], stream)
+        ctx.hdg_lincomb([self.Un] + self.stages, [1.0 - sum(e)] + list(e), st.U, stream)
+        return hists

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "hdg.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hdg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hdg_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_hot_path_calls():

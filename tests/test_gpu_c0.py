@@ -83,8 +83,9 @@ def test_assembled_trace_system(c0):
     assert num / den <= RTOL_FP64
     gs = assembled_g_scale(c0["wl"], [c0["ora"][e]["gK"] for e in range(c0["wl"].mesh.n_elem)])
     eg = np.linalg.norm(gpu["g"] - ts.g) / np.linalg.norm(gs)
-    print(f"  g: {np.linalg.norm(gpu['g'] - ts.g) / np.linalg.norm(ts.g):.3e} of |g|, {eg:.3e} of sum |g^K|")
-    assert eg <= RTOL_FP64
+    egp = np.linalg.norm(gpu["g"] - ts.g) / np.linalg.norm(ts.g)
+    print(f"  g: {egp:.3e} of |g|, {eg:.3e} of sum |g^K|")
+    assert eg <= RTOL_FP64 and egp <= RTOL_FP64
 
 
 def test_face_matvec(c0):
@@ -123,11 +124,22 @@ def test_gmres_same_inputs(c0):
 
 
 def test_gmres_end_to_end(c0):
-    """Whole chain against the oracle's own S and g: the increment inherits the
-    rounding of g (a sum of cancelling element terms), amplified by the solve."""
-    gpu = c0["gpu"]
-    e = assert_rel(gpu["dUhat"], c0["x"], 1e-10, "dUhat end to end")
-    assert e <= 1e-10
+    """Whole chain against the oracle's own S and g.  GMRES(30) converges to
+    rounding on this mesh (both histories checked), so the increment is the
+    solution of S x = g and differs from the oracle's by the first-order effect
+    of the S and g differences, ||S^{-1} [(g_gpu - g) - (S_gpu - S) x]||
+    (computed with the oracle's GMRES on its own S), plus 1e-12 of rounding."""
+    gpu, wl, ts, x, hx = c0["gpu"], c0["wl"], c0["ts"], c0["x"], c0["hist"]
+    assert hx[-1] <= 1e-12 * hx[0] and gpu["hist"][-1] <= 1e-12 * gpu["hist"][0]
+    tsg = O.TraceSystem.from_blocks(wl, bsr_blocks(c0["st"].ctx, gpu["S"]), gpu["g"])
+    d = (gpu["g"] - ts.g) - (tsg.matvec(x) - ts.matvec(x))
+    dx, dh = O.gmres(ts, d, wl.gmres_m)
+    assert dh[-1] <= 1e-12 * dh[0]
+    err = np.linalg.norm(gpu["dUhat"] - x)
+    pred = np.linalg.norm(dx)
+    nx = np.linalg.norm(x)
+    print(f"  dUhat end to end: {err / nx:.3e}; first-order effect of the S, g differences {pred / nx:.3e}")
+    assert err <= 2.0 * pred + RTOL_FP64 * nx
 
 
 def test_recovery(c0):
@@ -141,7 +153,7 @@ def test_recovery(c0):
         _, ep = recovery_error(wl, e, ora[e]["X"], gpu["dUhat"], got)
         wb, wf, wp = max(wb, b), max(wf, fr), max(wp, ep)
     print(f"  d(Q,U): backward error {wb:.2f} of n u, forward error {wf:.2f} of its bound, {wp:.2e} of its norm")
-    assert wb <= 1.0 and wf <= 1.0
+    assert wb <= 1.0 and wf <= 1.0 and wp <= RTOL_FP64
 
 
 def test_bitwise_reproducible_and_chunk_independent(c0):
