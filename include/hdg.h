@@ -150,7 +150,7 @@ int64_t hdg_layout_length(const hdg_ctx *ctx, int kind);
  * of ne elements starting at e0), 2 hdg_asm_setup, 3 hdg_asm_block_apply,
  * 4 hdg_gmres / hdg_gmres_x0 (with Krylov dimension m = ne), 5 hdg_rb_guess
  * (with ne = the largest basis size used), 6 hdg_residual_gather /
- * hdg_residual_norm. */
+ * hdg_residual_norm, 7 hdg_av_field. */
 int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, size_t *bytes);
 
 /*
@@ -317,6 +317,40 @@ int hdg_state_admissible(hdg_ctx *ctx, double alpha, const double *U, const doub
  */
 int hdg_lincomb(hdg_ctx *ctx, int k, const double *const *v, const double *coef, double *out, int64_t n,
                 void *stream);
+
+/*
+ * Artificial-viscosity field (eq. av-coeffs and the smoothing operator S_h of
+ * section 2.1; lagged: computed from a state and then held fixed as the nu
+ * input of hdg_local_residual_jacobian).  At every node of element e (degree
+ * k = p_e), from U and its gradient Q:
+ *   dv_i/dx_j = (q_{1+i,j} - v_i q_{0,j}) / rho,  div = dv_k/dx_k,
+ *   omega = |curl v|,  c* = sqrt(gamma p* / rho*), rho* = max(rho, rho_min),
+ *   p* = max(p, p_min),  Ld = max(-div, 0) (compression),  Lw = max(omega, 0),
+ *   s = sqrt(h_m / k) (Ld / c*) Ld^2 / (Ld^2 + Lw^2 + eps),
+ *   value = c_av min(max(s, 0), s_max);
+ * nu_raw[e] = the maximum over the element's nodes (the raw elemental
+ * viscosity).  Smoothing, smooth_iters >= 1 times: each vertex takes the mean
+ * of the elemental values of the elements sharing it (vertices are identified
+ * through every two-sided face, periodic pairs included), and between passes
+ * each element takes the mean of its 8 vertex values; nu (node array) is the
+ * trilinear interpolant of the final vertex values at each element's nodes, so
+ * it is continuous across faces.  smooth_iters = 0 gives nu = nu_raw[e] at
+ * every node of e.  nu_raw (device, n_elem) may be NULL.  Workspace op 7.
+ * Readings of the paper's unspecified limiter L, c* and the smoothing are
+ * these; the paper's supersonic Taylor-Green case uses c_av = 2e-3,
+ * h_m = 2 pi / N and two smoothing iterations.
+ */
+typedef struct hdg_av_params {
+    double c_av;      /* AV coefficient                                 */
+    double h_m;       /* sensor length scale                            */
+    double eps;       /* regularisation of the Ducros factor (> 0)     */
+    double s_max;     /* upper bound of the limited sensor (> 0, may be HUGE_VAL) */
+    double rho_min;   /* lower bounds of the regularised state (> 0)    */
+    double p_min;
+    int smooth_iters; /* 0..64                                          */
+} hdg_av_params;
+int hdg_av_field(hdg_ctx *ctx, const hdg_av_params *params, const double *U, const double *Q, double *nu_raw,
+                 double *nu, void *work, size_t work_bytes, void *stream);
 
 /*
  * Nonlinear residual norm of eq. nonlinear-residual.  hdg_residual_gather, for

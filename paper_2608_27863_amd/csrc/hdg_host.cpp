@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <vector>
@@ -178,6 +179,10 @@ int upload(hdg_ctx *ctx, const std::vector<T> &h, const T **dst) {
 int trace_size(int pf) { return 5 * (pf + 1) * (pf + 1); }
 
 }  // namespace
+
+namespace hdg {
+void gll_nodes(int p, double *r) { lobatto_nodes(p, r); }
+}  // namespace hdg
 
 // ====================================================================== API
 extern "C" {
@@ -409,6 +414,47 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
             face_src.insert(face_src.end(), fs[F].begin(), fs[F].end());
         }
     }
+    // ---- vertex classes for the artificial-viscosity smoothing: the corners of
+    // the two sides of every two-sided face (periodic pairs included) are the
+    // same vertices; matching corners have the same tangential position
+    std::vector<int> av_corner(8 * ne), av_src_ptr, av_src;
+    int n_vclass = 0;
+    {
+        std::vector<int> parent(m->n_vert);
+        for (int v = 0; v < m->n_vert; ++v) parent[v] = v;
+        std::function<int(int)> root = [&](int v) {
+            while (parent[v] != v) v = parent[v] = parent[parent[v]];
+            return v;
+        };
+        for (int F = 0; F < nf; ++F) {
+            const int e0 = ctx->face_elem[4 * F], l0 = ctx->face_elem[4 * F + 1];
+            const int e1 = ctx->face_elem[4 * F + 2], l1 = ctx->face_elem[4 * F + 3];
+            if (e1 < 0) continue;
+            const int d = l0 / 2;
+            for (int c = 0; c < 8; ++c) {
+                if (((c >> d) & 1) != (l0 & 1)) continue;
+                const int c1 = (c & ~(1 << d)) | ((l1 & 1) << d);
+                const int a = root(m->elem_vert[8 * e0 + c]), b = root(m->elem_vert[8 * e1 + c1]);
+                if (a != b) parent[std::max(a, b)] = std::min(a, b);
+            }
+        }
+        std::vector<int> id(m->n_vert, -1);
+        for (int e = 0; e < ne; ++e)
+            for (int c = 0; c < 8; ++c) {
+                const int r = root(m->elem_vert[8 * e + c]);
+                if (id[r] < 0) id[r] = n_vclass++;
+                av_corner[8 * e + c] = id[r];
+            }
+        std::vector<std::vector<int>> src(n_vclass);
+        for (int e = 0; e < ne; ++e)
+            for (int c = 0; c < 8; ++c) src[av_corner[8 * e + c]].push_back(e);
+        av_src_ptr.assign(n_vclass + 1, 0);
+        for (int k = 0; k < n_vclass; ++k) {
+            av_src_ptr[k + 1] = av_src_ptr[k] + (int)src[k].size();
+            av_src.insert(av_src.end(), src[k].begin(), src[k].end());
+        }
+    }
+    ctx->n_vclass = n_vclass;
     // ---- upload (first HIP call: everything above is host-side validation and set-up)
     if (hipGetDevice(&ctx->device) != hipSuccess) return fail(HDG_ERR_DEVICE);
     if (hdg::asm_scratch_init(ctx->device) != 0) return fail(HDG_ERR_DEVICE);
@@ -445,6 +491,10 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
     UP(face_src_ptr, face_src_ptr);
     UP(face_src, face_src);
     UP(asm_blk, asm_blk);
+    UP(av_corner, av_corner);
+    UP(av_src_ptr, av_src_ptr);
+    UP(av_src, av_src);
+    dm.n_vclass = n_vclass;
 #undef UP
     ctx->bsr_row_ptr64.assign(ctx->bsr_row_ptr.begin(), ctx->bsr_row_ptr.end());
     ctx->bsr_col64.assign(ctx->bsr_col.begin(), ctx->bsr_col.end());
@@ -519,6 +569,7 @@ int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, siz
             *bytes = hdg::rb_work_bytes(ctx, ne);
             return HDG_OK;
         case 6: *bytes = hdg::resid_work_bytes(ctx); return HDG_OK;
+        case 7: *bytes = hdg::av_work_bytes(ctx); return HDG_OK;
         default: return HDG_ERR_INVALID_ARGUMENT;
     }
 }
@@ -647,6 +698,17 @@ int hdg_residual_gather(hdg_ctx *ctx, int e0, int ne, const double *E, void *wor
     if (!chunk_ok(ctx, e0, ne) || !E) return HDG_ERR_INVALID_ARGUMENT;
     if (!work || work_bytes < hdg::resid_work_bytes(ctx)) return HDG_ERR_WORKSPACE;
     return dev_status(hdg::launch_resid_elem(ctx, e0, ne, E, work, (hipStream_t)stream));
+}
+
+int hdg_av_field(hdg_ctx *ctx, const hdg_av_params *ap, const double *U, const double *Q, double *nu_raw,
+                 double *nu, void *work, size_t work_bytes, void *stream) {
+    if (!ctx || !ap || !U || !Q || !nu) return HDG_ERR_INVALID_ARGUMENT;
+    if (!(ap->c_av >= 0.0) || !(ap->h_m > 0.0) || !(ap->eps > 0.0) || !(ap->s_max > 0.0) ||
+        !(ap->rho_min > 0.0) || !(ap->p_min > 0.0) || ap->smooth_iters < 0 || ap->smooth_iters > 64)
+        return HDG_ERR_INVALID_ARGUMENT;
+    if (!work || work_bytes < hdg::av_work_bytes(ctx)) return HDG_ERR_WORKSPACE;
+    const hdg::AvParams p{ap->c_av, ap->h_m, ap->eps, ap->s_max, ap->rho_min, ap->p_min, ap->smooth_iters};
+    return dev_status(hdg::launch_av_field(ctx, p, U, Q, nu_raw, nu, work, (hipStream_t)stream));
 }
 
 int hdg_residual_norm(hdg_ctx *ctx, void *work, size_t work_bytes, double *norms, void *stream) {

@@ -68,6 +68,13 @@ struct DevMesh {
     const int *face_src_ptr;   // [n_face+1] elements touching each face
     const int *face_src;       // [n][2]: elem, local face
     const int *asm_blk;        // [n_elem][36]: bsr block index of (face a, face b)
+    // artificial-viscosity smoothing: element corners grouped into vertex
+    // classes (vertices identified through every two-sided face, periodic
+    // pairs included)
+    int n_vclass;
+    const int *av_corner;      // [n_elem][8] vertex class of each corner (tensor order)
+    const int *av_src_ptr;     // [n_vclass+1]
+    const int *av_src;         // elements touching each class, ascending
 };
 
 struct Phys {
@@ -91,6 +98,7 @@ struct hdg_ctx {
     int n_elem = 0, n_face = 0;
     hdg::Phys phys{};
     int max_n = 0, max_f = 0, max_b = 0, max_p = 0;
+    int n_vclass = 0;  // vertex classes of the artificial-viscosity smoothing
     bool uniform_p = true;
     bool repeated_face = false;  // some element meets the same face twice
     std::vector<int> elem_p, face_p, elem_face, face_elem, face_bc, toff, elem_n, elem_f;
@@ -144,6 +152,14 @@ int launch_resid_norm(const hdg_ctx *ctx, void *work, double *out, hipStream_t s
 int launch_admissible(const hdg_ctx *ctx, double alpha, const double *U, const double *dQU, int *flag,
                       hipStream_t s);
 size_t gmres_work_bytes(const hdg_ctx *ctx, int m);
+struct AvParams {
+    double c_av, h_m, eps, s_max, rho_min, p_min;
+    int smooth_iters;
+};
+size_t av_work_bytes(const hdg_ctx *ctx);
+void gll_nodes(int p, double *r);  // Gauss-Lobatto nodes of degree p on [-1, 1]
+int launch_av_field(const hdg_ctx *ctx, const AvParams &ap, const double *U, const double *Q, double *nu_raw,
+                    double *nu, void *work, hipStream_t s);
 int launch_recover(const hdg_ctx *ctx, int prec, int e0, int ne, const double *E,
                    const double *dUhat, double *dQU, hipStream_t s);
 }  // namespace hdg

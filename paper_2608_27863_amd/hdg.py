@@ -27,7 +27,7 @@ EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_
            "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior",
            "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy",
            "hdg_asm_block_apply_noalloc", "hdg_gmres_x0", "hdg_rb_guess", "hdg_rb_insert", "hdg_state_update",
-           "hdg_state_admissible", "hdg_lincomb", "hdg_residual_gather", "hdg_residual_norm"]
+           "hdg_state_admissible", "hdg_lincomb", "hdg_residual_gather", "hdg_residual_norm", "hdg_av_field"]
 
 RB_MAX = 32
 
@@ -61,6 +61,12 @@ class _NewtonArgs(ctypes.Structure):
                 ("Sinv", _vp), ("asm_info", _vp), ("asm_work", _vp), ("asm_work_bytes", ctypes.c_size_t),
                 ("gmres_work", _vp), ("gmres_work_bytes", ctypes.c_size_t),
                 ("dUhat", _vp), ("res_hist", _vp), ("dQU", _vp)]
+
+
+class _AvParams(ctypes.Structure):
+    _fields_ = [("c_av", ctypes.c_double), ("h_m", ctypes.c_double), ("eps", ctypes.c_double),
+                ("s_max", ctypes.c_double), ("rho_min", ctypes.c_double), ("p_min", ctypes.c_double),
+                ("smooth_iters", _i)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -103,6 +109,7 @@ def load_library(path: str = LIB_PATH):
                               _vp]
     L.hdg_residual_gather.argtypes = [_vp, _i, _i, _vp, _vp, ctypes.c_size_t, _vp]
     L.hdg_residual_norm.argtypes = [_vp, _vp, ctypes.c_size_t, _vp, _vp]
+    L.hdg_av_field.argtypes = [_vp, ctypes.POINTER(_AvParams), _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     for name in EXPORTS:
         if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length", "hdg_graph_destroy"):
             getattr(L, name).restype = _i
@@ -349,6 +356,19 @@ class Context:
         rc = self.L.hdg_residual_norm(self.h, _ptr(work, None, None, "work"), work.numel() * work.element_size(),
                                       _ptr(norms, torch.float64, 3, "norms"), _stream(stream))
         _check(rc, "hdg_residual_norm")
+
+    def hdg_av_field(self, params, U, Q, nu, work, nu_raw=None, stream=None):
+        """params: dict with c_av, h_m, eps, s_max, rho_min, p_min, smooth_iters."""
+        import torch
+        f64 = torch.float64
+        nn = int(self.layout["node_off"][-1])
+        ap = _AvParams(float(params["c_av"]), float(params["h_m"]), float(params["eps"]), float(params["s_max"]),
+                       float(params["rho_min"]), float(params["p_min"]), int(params["smooth_iters"]))
+        rc = self.L.hdg_av_field(self.h, ctypes.byref(ap), _ptr(U, f64, 5 * nn, "U"), _ptr(Q, f64, 15 * nn, "Q"),
+                                 _ptr(nu_raw, f64, self.n_elem, "nu_raw") if nu_raw is not None else None,
+                                 _ptr(nu, f64, nn, "nu"), _ptr(work, None, None, "work"),
+                                 work.numel() * work.element_size(), _stream(stream))
+        _check(rc, "hdg_av_field")
 
     # ------------------------------------------------------- whole step
     def newton_args(self, st):

@@ -241,12 +241,18 @@ class DirkStepper:
     d_ii M (U - Un) is the stage's mass term) and solves from the previous
     stage's state; then U <- (1 - sum_j e_j) U^n + sum_j e_j U^{n,j}, keeping Q
     and Uhat of the last stage (the tableau is stiffly accurate: e = (0, 0, 1)).
-    The context's alpha must be d_ii."""
+    The context's alpha must be d_ii.  With `av` (hdg_av_field parameters:
+    c_av, h_m, eps, s_max, rho_min, p_min, smooth_iters) the artificial
+    viscosity is recomputed from the state at the start of each step and held
+    fixed during it (lagged)."""
 
-    def __init__(self, solver):
+    def __init__(self, solver, av=None):
         import torch
         self.solver = solver
         st = solver.st
+        self.av = av
+        if av is not None:
+            self.av_work = torch.empty(st.ctx.workspace_size(7), dtype=torch.uint8, device=st.E.device)
         self.A, self.b, self.d, self.e = alexander_dirk()
         if abs(st.wl.alpha - self.d[0][0]) > 1e-12 * self.d[0][0]:
             raise ValueError("the context's alpha must equal d_ii = 1 / gamma of the tableau")
@@ -255,6 +261,8 @@ class DirkStepper:
 
     def step(self, stream=None):
         st, ctx, d, e = self.solver.st, self.solver.st.ctx, self.d, self.e
+        if self.av is not None:
+            ctx.hdg_av_field(self.av, st.U, st.Q, st.nu, self.av_work, stream=stream)
         ctx.hdg_lincomb([st.U], [1.0], self.Un, stream)
         hists = []
         for i in range(3):

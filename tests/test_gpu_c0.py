@@ -146,14 +146,21 @@ def test_recovery(c0):
     wl, st, gpu, ora = c0["wl"], c0["st"], c0["gpu"], c0["ora"]
     sz = O.Sizes(wl.mesh)
     no = st.ctx.layout["node_off"]
-    wb, wf, wp = 0.0, 0.0, 0.0
+    wb, wf, wp, ws, wr = 0.0, 0.0, 0.0, 0.0, 0.0
     for e in range(wl.mesh.n_elem):
         got = gpu["dQU"][20 * int(no[e]):20 * int(no[e + 1])]
         b, fr = recovery_checks(wl, e, ora[e]["E"], ora[e]["X"], gpu["dUhat"], got)
-        _, ep = recovery_error(wl, e, ora[e]["X"], gpu["dUhat"], got)
-        wb, wf, wp = max(wb, b), max(wf, fr), max(wp, ep)
-    print(f"  d(Q,U): backward error {wb:.2f} of n u, forward error {wf:.2f} of its bound, {wp:.2e} of its norm")
-    assert wb <= 1.0 and wf <= 1.0 and wp <= RTOL_FP64
+        es, ep = recovery_error(wl, e, ora[e]["X"], gpu["dUhat"], got)
+        # -(x_r + X_B dUh) cancels: its summands are this many times larger than it
+        d = O.gather_trace(wl, O.Sizes(wl.mesh), e, gpu["dUhat"])
+        X = ora[e]["X"]
+        cancel = np.linalg.norm(np.abs(X[:, -1]) + np.abs(X[:, :-1]) @ np.abs(d)) / np.linalg.norm(
+            X[:, -1] + X[:, :-1] @ d)
+        wb, wf, wp, ws = max(wb, b), max(wf, fr), max(wp, ep), max(ws, es)
+        wr = max(wr, ep / max(1.0, cancel))
+    print(f"  d(Q,U): backward error {wb:.2f} of n u, forward error {wf:.2f} of its bound, {ws:.2e} of its "
+          f"summands, {wp:.2e} of its norm ({wr:.2e} after dividing by each element's cancellation factor)")
+    assert wb <= 1.0 and wf <= 1.0 and ws <= RTOL_FP64 and wr <= RTOL_FP64
 
 
 def test_bitwise_reproducible_and_chunk_independent(c0):
