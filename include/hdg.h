@@ -102,9 +102,35 @@ typedef struct hdg_mesh_desc {
     const int *face_elem;        /* host [n_face][2][2]: (elem, local face) of side 0
                                     and side 1; side 1 = (-1,-1) on a boundary face.
                                     The face normal points out of side 0.              */
-    const signed char *face_bc;  /* host [n_face]: 0 interior/periodic, 1 Dirichlet    */
+    const signed char *face_bc;  /* host [n_face]: boundary type, see below             */
     const signed char *elem_p;   /* host [n_elem]: degree 1..4                         */
+    const double *elem_geom;     /* host [n_elem][27][3] or NULL: curved (triquadratic)
+                                    geometry, the element's map through 27 nodes in
+                                    tensor order (x fastest) at reference coordinates
+                                    -1, 0, 1; NULL = the trilinear map of the vertices.
+                                    Vertices still define the topology; nodes on shared
+                                    faces must coincide (section 2.2: curved elements). */
 } hdg_mesh_desc;
+
+/* Boundary types (face_bc of a one-sided face; the weak boundary statement
+ * b^ of eq. hdg-trace replaces the numerical flux in the face's trace
+ * equations, integrated against mu with the face's |N| dS; the conservation
+ * equations keep the numerical flux fh of eq. num-flux-hdg evaluated with the
+ * trace), following the boundary-condition paragraph of section 2.1:
+ *   HDG_BC_STATE      b^ = uh - ub          prescribed exterior state (far field,
+ *                                           supersonic inflow); reads Ub
+ *   HDG_BC_EXTRAP     b^ = uh - u           interior state extrapolated
+ *                                           (supersonic outflow)
+ *   HDG_BC_WALL_T     b^ = (rho^ - rho, m^, rho^E^ - rho^ e_w)
+ *                                           no-slip isothermal wall; e_w = the internal
+ *                                           energy of ub (reads Ub)
+ *   HDG_BC_WALL_ADIAB b^ = (rho^ - rho, m^, fh_energy)
+ *                                           no-slip adiabatic wall (no energy flux)
+ *   HDG_BC_SYMMETRY   b^ = (rho^ - rho, m^ - (I - n n^T) m, rho^E^ - rhoE)
+ *                                           zero normal velocity, tangential state
+ *                                           from the interior                        */
+enum { HDG_BC_NONE = 0, HDG_BC_STATE = 1, HDG_BC_EXTRAP = 2, HDG_BC_WALL_T = 3, HDG_BC_WALL_ADIAB = 4,
+       HDG_BC_SYMMETRY = 5 };
 
 /* Physical and time-discretisation constants (section 2, section 5). */
 typedef struct hdg_phys {
@@ -163,10 +189,10 @@ int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, siz
  *   R_u[c,i]     = alpha int_K (u-u^n)_c phi_i - dt int_K (F^c - F^v)_cj d_j phi_i
  *                  + dt int_dK fh_c phi_i
  *   R_uh^K[F,c,a]= int_F fh_c mu_a            (interior / periodic faces)
- *                = int_F (uh - ub)_c mu_a     (Dirichlet faces, face_bc = 1)
+ *                = int_F b^_c mu_a            (boundary faces, b^ per face_bc above)
  *   fh = (F^c(uh) - F^v(uh, q)) . n + tau (u - uh),  F^v includes nu q.
- * nu is frozen (no derivative).  Ub is read only on Dirichlet faces (may be
- * NULL when the mesh has none).  E points at element e0's system.  `work`
+ * nu is frozen (no derivative).  Ub is read only on faces of types
+ * HDG_BC_STATE and HDG_BC_WALL_T (may be NULL when the mesh has none).  E points at element e0's system.  `work`
  * (hdg_workspace_size op 0) holds the quadrature-point fluxes and Jacobians
  * (the point kernel's output, read by the assembly kernel).
  */
@@ -388,7 +414,7 @@ int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E
  * (element e at E_off[e]); qp_work and cond_work must be at least the
  * workspace of the largest chunk (hdg_workspace_size ops 0 and 1), asm_work
  * op 2 with asm_prec, gmres_work op 4 with ne = gmres_m.  Ub may be NULL only
- * on a mesh without Dirichlet faces.  Sinv holds doubles for asm_prec =
+ * on a mesh without faces that read Ub.  Sinv holds doubles for asm_prec =
  * HDG_FP64 and floats for HDG_MIXED.  The chunk arrays are copied.
  */
 typedef struct hdg_newton_args {

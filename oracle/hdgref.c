@@ -239,6 +239,30 @@ static void trilinear_jac(const double *X8, const double *xi, double J[3][3], do
     }
 }
 
+/* Geometry map of order g (1: the 8 vertices, trilinear; 2: 27 nodes,
+ * triquadratic), nodes in tensor order at reference coordinates equispaced on
+ * [-1, 1]: x(xi) = sum_abc X_abc l_a(xi_0) l_b(xi_1) l_c(xi_2) with the Lagrange
+ * polynomials of those coordinates (the curved high-order map of section 2.2). */
+static void geom_jac(int g, const double *Xg, const double *xi, double J[3][3], double *x)
+{
+    if (g == 1) { trilinear_jac(Xg, xi, J, x); return; }
+    double r[3] = { -1.0, 0.0, 1.0 }, l[3][3], dl[3][3];
+    for (int d = 0; d < 3; ++d) lagrange(2, r, xi[d], l[d], dl[d]);
+    for (int i = 0; i < 3; ++i) { x[i] = 0.0; for (int d = 0; d < 3; ++d) J[i][d] = 0.0; }
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                const double *X = Xg + 3 * (a + 3 * (b + 3 * c));
+                double N = l[0][a] * l[1][b] * l[2][c];
+                double dN[3] = { dl[0][a] * l[1][b] * l[2][c], l[0][a] * dl[1][b] * l[2][c],
+                                 l[0][a] * l[1][b] * dl[2][c] };
+                for (int i = 0; i < 3; ++i) {
+                    x[i] += N * X[i];
+                    for (int d = 0; d < 3; ++d) J[i][d] += dN[d] * X[i];
+                }
+            }
+}
+
 static double inv3(double J[3][3], double G[3][3])
 {
     /* G = J^{-1}: G[d][j] = d xi_d / d x_j */
@@ -275,12 +299,15 @@ static void face_normal(double J[3][3], int d, double s, double *N)
 int hdgref_trace_size(int pf) { return 5 * (pf + 1) * (pf + 1); }
 
 /*
- * p: element degree; pf[6]: face degrees; bc[6]: 1 = Dirichlet-state face;
- * X8: 8 vertices (tensor order) * 3; prm: gamma, Pr, Re, Mach, tau, dt, alpha, visc_law;
+ * p: element degree; pf[6]: face degrees; bc[6]: boundary type of each face (0 interior
+ * or periodic; 1 prescribed state, 2 extrapolated state, 3 isothermal wall, 4 adiabatic
+ * wall, 5 symmetry; see the boundary residual below);
+ * g, Xg: geometry order (1 or 2) and its 8 or 27 nodes (tensor order) * 3;
+ * prm: gamma, Pr, Re, Mach, tau, dt, alpha, visc_law;
  * Q [15][N_p], U, Un [5][N_p], nu [N_p]; Uh, Ub: element trace order [sum_lf 5 N_fp];
  * E: (n+f) x (n+f+1) column-major, overwritten.
  */
-int hdgref_element_system(int p, const int *pf, const int *bc, const double *X8, const double *prm,
+int hdgref_element_system(int p, const int *pf, const int *bc, int g, const double *Xg, const double *prm,
                           const double *Q, const double *U, const double *Un, const double *nu,
                           const double *Uh, const double *Ub, double *E)
 {
@@ -307,7 +334,7 @@ int hdgref_element_system(int p, const int *pf, const int *bc, const double *X8,
         double xi[3] = { xg[g0], xg[g1], xg[g2] };
         double w = wg[g0] * wg[g1] * wg[g2];
         double J[3][3], G[3][3], xx[3];
-        trilinear_jac(X8, xi, J, xx);
+        geom_jac(g, Xg, xi, J, xx);
         double det = inv3(J, G);
         double W = w * det;
         double l[3][8], dl[3][8];
@@ -383,7 +410,7 @@ int hdgref_element_system(int p, const int *pf, const int *bc, const double *X8,
             xi[t1] = xf[s1];
             double ws = wf[s0] * wf[s1];
             double J[3][3], xx[3], N[3];
-            trilinear_jac(X8, xi, J, xx);
+            geom_jac(g, Xg, xi, J, xx);
             face_normal(J, d, sgn, N);
             double area = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
             double l[3][8];
@@ -406,7 +433,7 @@ int hdgref_element_system(int p, const int *pf, const int *bc, const double *X8,
             for (int c = 0; c < 5; ++c)
                 for (int a = 0; a < Nfp; ++a) {
                     uh[c] += mu[a] * Uh[toff[lf] + c * Nfp + a];
-                    if (bc[lf]) ub[c] += mu[a] * Ub[toff[lf] + c * Nfp + a];
+                    if (bc[lf] == 1 || bc[lf] == 3) ub[c] += mu[a] * Ub[toff[lf] + c * Nfp + a];
                 }
             dual uhd[5], qd[15], Fc[5][3], Fv[5][3], fh[5];
             for (int c = 0; c < 5; ++c) uhd[c] = dvar(uh[c], 20 + c);
@@ -417,6 +444,53 @@ int hdgref_element_system(int p, const int *pf, const int *bc, const double *X8,
                 dual fc = dscale(dsub(dvar(u[c], c), uhd[c]), P.tau * area);
                 for (int j = 0; j < 3; ++j) fc = dadd(fc, dscale(dsub(Fc[c][j], Fv[c][j]), N[j]));
                 fh[c] = fc;
+            }
+            /* boundary residual b^ of eq. hdg-trace on a boundary face (times |N|):
+             *  1 prescribed state:       uh - ub
+             *  2 extrapolated state:     uh - u
+             *  3 no-slip isothermal wall: (rho^ - rho, m^, rho^E^ - rho^ e_w), e_w the
+             *    internal energy of the prescribed state ub
+             *  4 no-slip adiabatic wall: (rho^ - rho, m^, f^_energy / |N|)
+             *  5 symmetry: (rho^ - rho, m^ - (I - n n^T) m, rho^E^ - rhoE) */
+            dual bh[5];
+            if (bc[lf]) {
+                dual ud[5];
+                for (int c = 0; c < 5; ++c) ud[c] = dvar(u[c], c);
+                double nn[3] = { N[0] / area, N[1] / area, N[2] / area };
+                switch (bc[lf]) {
+                case 1:
+                    for (int c = 0; c < 5; ++c) bh[c] = dscale(dsub(uhd[c], dconst(ub[c])), area);
+                    break;
+                case 2:
+                    for (int c = 0; c < 5; ++c) bh[c] = dscale(dsub(uhd[c], ud[c]), area);
+                    break;
+                case 3: case 4: {
+                    bh[0] = dscale(dsub(uhd[0], ud[0]), area);
+                    for (int i = 1; i < 4; ++i) bh[i] = dscale(uhd[i], area);
+                    if (bc[lf] == 3) {
+                        double ew = ub[4] / ub[0] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2] + ub[3] * ub[3]) / (ub[0] * ub[0]);
+                        bh[4] = dscale(dsub(uhd[4], dscale(uhd[0], ew)), area);
+                    } else {
+                        bh[4] = fh[4];
+                    }
+                    break;
+                }
+                case 5: {
+                    bh[0] = dscale(dsub(uhd[0], ud[0]), area);
+                    for (int i = 0; i < 3; ++i) {
+                        dual t = uhd[1 + i];
+                        for (int j = 0; j < 3; ++j) {
+                            double pij = (i == j ? 1.0 : 0.0) - nn[i] * nn[j];
+                            t = dsub(t, dscale(ud[1 + j], pij));
+                        }
+                        bh[1 + i] = dscale(t, area);
+                    }
+                    bh[4] = dscale(dsub(uhd[4], ud[4]), area);
+                    break;
+                }
+                default:
+                    return -1;
+                }
             }
             for (int i = 0; i < Np; ++i) {
                 if (phi[i] == 0.0) continue;
@@ -449,23 +523,18 @@ int hdgref_element_system(int p, const int *pf, const int *bc, const double *X8,
             for (int c = 0; c < 5; ++c)
                 for (int a = 0; a < Nfp; ++a) {
                     int row = n + toff[lf] + c * Nfp + a;
-                    if (bc[lf]) {
-                        /* Dirichlet state: < uh - ub, mu > */
-                        EL(row, colR) += ws * area * (uh[c] - ub[c]) * mu[a];
-                        for (int b = 0; b < Nfp; ++b)
-                            EL(row, n + toff[lf] + c * Nfp + b) += ws * area * mu[a] * mu[b];
-                        continue;
-                    }
-                    EL(row, colR) += ws * fh[c].v * mu[a];
+                    /* interior face: < f^, mu >; boundary face: < b^, mu > */
+                    const dual *r = bc[lf] ? bh : fh;
+                    EL(row, colR) += ws * r[c].v * mu[a];
                     for (int s = 0; s < 20; ++s) {
                         int slot = (s < 15) ? 5 + s : s - 15;
-                        double coef = ws * fh[c].d[slot] * mu[a];
+                        double coef = ws * r[c].d[slot] * mu[a];
                         if (coef == 0.0) continue;
                         for (int k = 0; k < Np; ++k) EL(row, s * Np + k) += coef * phi[k];
                     }
                     for (int c2 = 0; c2 < 5; ++c2)
                         for (int b = 0; b < Nfp; ++b)
-                            EL(row, n + toff[lf] + c2 * Nfp + b) += ws * fh[c].d[20 + c2] * mu[a] * mu[b];
+                            EL(row, n + toff[lf] + c2 * Nfp + b) += ws * r[c].d[20 + c2] * mu[a] * mu[b];
                 }
         }
     }
@@ -476,7 +545,7 @@ int hdgref_element_system(int p, const int *pf, const int *bc, const double *X8,
 }
 
 /* Volume quadrature data for pins: |K| and the element mass matrix row sums. */
-double hdgref_element_volume(int p, const double *X8)
+double hdgref_element_volume(int p, int g, const double *Xg)
 {
     double xg[8], wg[8];
     hdgref_gauss(p + 2, xg, wg);
@@ -485,7 +554,7 @@ double hdgref_element_volume(int p, const double *X8)
         for (int g1 = 0; g1 < p + 2; ++g1)
             for (int g0 = 0; g0 < p + 2; ++g0) {
                 double xi[3] = { xg[g0], xg[g1], xg[g2] }, J[3][3], G[3][3], xx[3];
-                trilinear_jac(X8, xi, J, xx);
+                geom_jac(g, Xg, xi, J, xx);
                 vol += wg[g0] * wg[g1] * wg[g2] * inv3(J, G);
             }
     return vol;

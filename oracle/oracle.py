@@ -51,7 +51,7 @@ def lib():
         if _lib is None:
             build()
             L = ctypes.CDLL(_LIB)
-            L.hdgref_element_system.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _dp, _dp,
+            L.hdgref_element_system.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
                                                 _dp, _dp, _dp, _dp]
             L.hdgref_element_system.restype = ctypes.c_int
             L.hdgref_condense.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
@@ -65,7 +65,7 @@ def lib():
             L.hdgref_gauss.argtypes = [ctypes.c_int, _dp, _dp]
             L.hdgref_gll.argtypes = [ctypes.c_int, _dp]
             L.hdgref_point_flux.argtypes = [_dp, _dp, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
-            L.hdgref_element_volume.argtypes = [ctypes.c_int, _dp]
+            L.hdgref_element_volume.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
             L.hdgref_element_volume.restype = ctypes.c_double
             _lib = L
     return _lib
@@ -137,6 +137,20 @@ def gather_trace(wl, sizes, e, vec):
     return np.concatenate(out)
 
 
+def element_geometry(mesh, e):
+    """(order, nodes) of element e's geometry map: the 8 vertices (trilinear), or
+    the mesh's 27 curved-geometry nodes (triquadratic) when it has them."""
+    geom = getattr(mesh, "elem_geom", None)
+    if geom is None:
+        return 1, _f64(mesh.vert_xyz[mesh.elem_vert[e]].ravel())
+    return 2, _f64(np.asarray(geom[e]).ravel())
+
+
+def element_volume(mesh, e):
+    g, Xg = element_geometry(mesh, e)
+    return lib().hdgref_element_volume(int(mesh.elem_p[e]), g, _p(Xg))
+
+
 def element_system(wl, e, sizes=None, U=None, Q=None, Uhat=None):
     """E^K = [[A, B, R_qu], [C, D, R_uh]] of element e (column-major, (n+f) x (n+f+1))."""
     sizes = sizes or Sizes(wl.mesh)
@@ -149,12 +163,12 @@ def element_system(wl, e, sizes=None, U=None, Q=None, Uhat=None):
     o = sizes.noff[e]
     pf = np.array([sizes.fp[F] for F in m.elem_face[e]], dtype=np.int32)
     bc = np.array([m.face_bc[F] for F in m.elem_face[e]], dtype=np.int32)
-    X8 = _f64(m.vert_xyz[m.elem_vert[e]].ravel())
+    g, Xg = element_geometry(m, e)
     n = 20 * Np
     f = sizes.f(e)
     E = np.zeros((n + f + 1) * (n + f))
     rc = lib().hdgref_element_system(
-        p, _p(pf, _ip), _p(bc, _ip), _p(X8), _p(params(wl)),
+        p, _p(pf, _ip), _p(bc, _ip), g, _p(Xg), _p(params(wl)),
         _p(_f64(Q[15 * o:15 * (o + Np)])), _p(_f64(U[5 * o:5 * (o + Np)])),
         _p(_f64(wl.Un[5 * o:5 * (o + Np)])), _p(_f64(wl.nu[o:o + Np])),
         _p(_f64(gather_trace(wl, sizes, e, Uhat))), _p(_f64(gather_trace(wl, sizes, e, wl.Ub))),

@@ -150,6 +150,33 @@ void map_jacobian(const double *X8, const double xi[3], double J[3][3]) {
     }
 }
 
+// Triquadratic map of 27 nodes (tensor order, x fastest; reference
+// coordinates -1, 0, 1 per direction): J[i][d] = dx_i/dxi_d.  The quadratic
+// Lagrange factors on {-1, 0, 1}: l0 = t(t-1)/2, l1 = 1 - t^2, l2 = t(t+1)/2.
+void map_jacobian27(const double *X27, const double xi[3], double J[3][3]) {
+    double l[3][3], dl[3][3];
+    for (int d = 0; d < 3; ++d) {
+        const double t = xi[d];
+        l[d][0] = 0.5 * t * (t - 1.0);
+        l[d][1] = 1.0 - t * t;
+        l[d][2] = 0.5 * t * (t + 1.0);
+        dl[d][0] = t - 0.5;
+        dl[d][1] = -2.0 * t;
+        dl[d][2] = t + 0.5;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int d = 0; d < 3; ++d) J[i][d] = 0.0;
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                const double *X = X27 + 3 * (a + 3 * (b + 3 * c));
+                const double g[3] = {dl[0][a] * l[1][b] * l[2][c], l[0][a] * dl[1][b] * l[2][c],
+                                     l[0][a] * l[1][b] * dl[2][c]};
+                for (int i = 0; i < 3; ++i)
+                    for (int d = 0; d < 3; ++d) J[i][d] += g[d] * X[i];
+            }
+}
+
 // Cofactor inverse: G = J^{-1}, returns det J.
 double invert3(const double J[3][3], double G[3][3]) {
     double C[3][3];
@@ -238,7 +265,7 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
     ctx->face_p.assign(nf, 0);
     for (int F = 0; F < nf; ++F) {
         ctx->face_bc[F] = m->face_bc[F];
-        if (m->face_bc[F] != 0 && m->face_bc[F] != 1) return fail(HDG_ERR_INVALID_ARGUMENT);
+        if (m->face_bc[F] < 0 || m->face_bc[F] > 5) return fail(HDG_ERR_INVALID_ARGUMENT);
         int e0 = ctx->face_elem[4 * F], l0 = ctx->face_elem[4 * F + 1];
         int e1 = ctx->face_elem[4 * F + 2], l1 = ctx->face_elem[4 * F + 3];
         if (e0 < 0 || e0 >= ne || l0 < 0 || l0 > 5) return fail(HDG_ERR_INVALID_ARGUMENT);
@@ -317,6 +344,11 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
         double X8[24];
         for (int v = 0; v < 8; ++v)
             for (int i = 0; i < 3; ++i) X8[3 * v + i] = m->vert_xyz[3 * m->elem_vert[8 * e + v] + i];
+        const double *X27 = m->elem_geom ? m->elem_geom + 81 * (size_t)e : nullptr;
+        auto jac = [&](const double xi[3], double J[3][3]) {
+            if (X27) map_jacobian27(X27, xi, J);
+            else map_jacobian(X8, xi, J);
+        };
         int p = ctx->elem_p[e], nq = p + 2, Nq = nq * nq * nq;
         double x[8], w[8];
         gauss_rule(nq, x, w);
@@ -326,7 +358,7 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
                 for (int g0 = 0; g0 < nq; ++g0) {
                     int g = g0 + nq * (g1 + nq * g2);
                     double xi[3] = {x[g0], x[g1], x[g2]}, J[3][3], G[3][3];
-                    map_jacobian(X8, xi, J);
+                    jac(xi, J);
                     double det = invert3(J, G);
                     if (!(det > 0.0)) return fail(HDG_ERR_INVALID_ARGUMENT);
                     vg[g] = w[g0] * w[g1] * w[g2] * det;
@@ -347,7 +379,7 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
                     xi[d] = sgn;
                     xi[t0] = xf[s0];
                     xi[t1] = xf[s1];
-                    map_jacobian(X8, xi, J);
+                    jac(xi, J);
                     double det = invert3(J, G);
                     if (!(det > 0.0)) return fail(HDG_ERR_INVALID_ARGUMENT);
                     // Nanson: n dS = det J J^{-T} n_ref dS_ref, n_ref = sgn e_d
@@ -575,6 +607,8 @@ int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, siz
 }
 
 static int dev_status(int hip_err) { return hip_err == 0 ? HDG_OK : HDG_ERR_DEVICE; }
+// boundary types that read the prescribed state Ub (prescribed state, isothermal wall)
+static bool needs_ub(int bc) { return bc == 1 || bc == 3; }
 
 int hdg_local_residual_jacobian(hdg_ctx *ctx, int e0, int ne, const double *Q, const double *U,
                                 const double *Un, const double *Uhat, const double *nu, const double *Ub,
@@ -582,7 +616,7 @@ int hdg_local_residual_jacobian(hdg_ctx *ctx, int e0, int ne, const double *Q, c
     if (!chunk_ok(ctx, e0, ne) || !Q || !U || !Un || !Uhat || !nu || !E || !work) return HDG_ERR_INVALID_ARGUMENT;
     for (int e = e0; e < e0 + ne; ++e)
         for (int lf = 0; lf < 6; ++lf)
-            if (ctx->face_bc[ctx->elem_face[6 * e + lf]] && !Ub) return HDG_ERR_INVALID_ARGUMENT;
+            if (needs_ub(ctx->face_bc[ctx->elem_face[6 * e + lf]]) && !Ub) return HDG_ERR_INVALID_ARGUMENT;
     size_t need;
     hdg_workspace_size(ctx, 0, HDG_FP64, e0, ne, &need);
     if (work_bytes < need) return HDG_ERR_WORKSPACE;
@@ -755,7 +789,7 @@ static int newton_check(hdg_ctx *ctx, const hdg_newton_args *a) {
         if (!seen[e]) return HDG_ERR_INVALID_ARGUMENT;
     if (!a->Ub)
         for (int F = 0; F < ctx->n_face; ++F)
-            if (ctx->face_bc[F]) return HDG_ERR_INVALID_ARGUMENT;
+            if (needs_ub(ctx->face_bc[F])) return HDG_ERR_INVALID_ARGUMENT;
     if (ctx->repeated_face) return HDG_ERR_UNSUPPORTED;
     if (a->asm_work_bytes < hdg::asm_setup_work_bytes(ctx, a->asm_prec)) return HDG_ERR_WORKSPACE;
     if (a->gmres_work_bytes < hdg::gmres_work_bytes(ctx, a->gmres_m)) return HDG_ERR_WORKSPACE;

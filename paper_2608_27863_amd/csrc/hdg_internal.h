@@ -32,9 +32,10 @@ __host__ __device__ inline int tbl_W(int nq, int g) { return kTblW + (nq - 3) * 
 //   face lf (lf = 0..5, points of that face)
 //           fjac [c 5][slot 25][s]     d(fh_c dS)/d(u 0..4, q 5..19, uh 20..24), weights included
 //           fres [c 5][s]              fh_c dS
-//           bres [c 5][s]              |N| w (uh - ub)_c   (Dirichlet faces)
+//           bres [c 5][s]              boundary residual w |N| b^_c (boundary faces)
 //           fuh  [c 5][s]              uh_c
-constexpr int kVJac = 400, kVRes = 80, kFJac = 125, kFPer = 140;
+//           bjac [c 5][slot 25][s]     d(b^_c)/d(u, q, uh), weights included (boundary faces)
+constexpr int kVJac = 400, kVRes = 80, kFJac = 125, kFPer = 265;
 
 // Device view of a context, passed by value to kernels.
 struct DevMesh {

@@ -256,7 +256,8 @@ __global__ void __launch_bounds__(64) k_qp_face(DevMesh dm, Phys P, int e0, cons
     const double *fg = dm.fgeo + dm.fgeo_off[6 * e + lf];
     double *out = qp + (qp_face_base(dm, e, lf, Nq) - dm.qp_off[e0]);
     const double *uh_g = Uhg + dm.face_off[F];
-    const double *ub_g = bc ? Ubg + dm.face_off[F] : nullptr;
+    const bool has_ub = (bc == 1 || bc == 3);  // boundary types that read prescribed data
+    const double *ub_g = has_ub ? Ubg + dm.face_off[F] : nullptr;
     for (int s = threadIdx.x; s < Nqf; s += blockDim.x) {
         const int s0 = s % nqf1, s1 = s / nqf1;
         double u[5] = {0, 0, 0, 0, 0}, q[15], nu = 0.0, uh[5] = {0, 0, 0, 0, 0}, ub[5] = {0, 0, 0, 0, 0};
@@ -280,7 +281,7 @@ __global__ void __launch_bounds__(64) k_qp_face(DevMesh dm, Phys P, int e0, cons
                 const int b = b0 + pf1 * b1;
                 for (int c = 0; c < 5; ++c) {
                     uh[c] += mu * uh_g[c * Nfp + b];
-                    if (bc) ub[c] += mu * ub_g[c * Nfp + b];
+                    if (has_ub) ub[c] += mu * ub_g[c * Nfp + b];
                 }
             }
         const double wN[3] = {fg[s], fg[Nqf + s], fg[2 * Nqf + s]}, wA = fg[3 * Nqf + s];
@@ -290,7 +291,7 @@ __global__ void __launch_bounds__(64) k_qp_face(DevMesh dm, Phys P, int e0, cons
         total_flux(uh, q, nu, P, st, Fl);
         for (int c = 0; c < 5; ++c) {
             out[(125 + c) * Nqf + s] = Fl[c][0] * wN[0] + Fl[c][1] * wN[1] + Fl[c][2] * wN[2] + P.tau * wA * (u[c] - uh[c]);
-            out[(130 + c) * Nqf + s] = bc ? wA * (uh[c] - ub[c]) : 0.0;
+            out[(130 + c) * Nqf + s] = 0.0;
             out[(135 + c) * Nqf + s] = uh[c];
         }
         // d fh / d u (element trace): tau |N| I
@@ -310,6 +311,62 @@ __global__ void __launch_bounds__(64) k_qp_face(DevMesh dm, Phys P, int e0, cons
             for (int c = 0; c < 5; ++c)
                 out[(25 * c + 20 + cp) * Nqf + s] =
                     dF[c][0] * wN[0] + dF[c][1] * wN[1] + dF[c][2] * wN[2] - ((c == cp) ? P.tau * wA : 0.0);
+        }
+        if (bc) {
+            // boundary residual b^ of eq. hdg-trace (weighted by w |N|) into slots 130+c, its
+            // derivatives d b^_c / d(u 0..4, q 5..19, uh 20..24) into 140 + 25 c + slot:
+            //  1 prescribed state uh - ub; 2 extrapolated state uh - u;
+            //  3 no-slip isothermal wall (rho^ - rho, m^, rho^E^ - rho^ e_w), e_w the internal
+            //    energy of the prescribed state; 4 no-slip adiabatic wall (rho^ - rho, m^, the
+            //    energy component of the numerical flux); 5 symmetry (rho^ - rho,
+            //    m^ - (I - n n^T) m, rho^E^ - rhoE)
+            double *bj = out + (int64_t)140 * Nqf + s;
+            for (int k = 0; k < 125; ++k) bj[(int64_t)k * Nqf] = 0.0;
+            auto J = [&](int c, int slot) -> double & { return bj[(int64_t)(25 * c + slot) * Nqf]; };
+            double br[5];
+            if (bc == 1 || bc == 2) {
+                for (int c = 0; c < 5; ++c) {
+                    br[c] = wA * (uh[c] - (bc == 1 ? ub[c] : u[c]));
+                    J(c, 20 + c) = wA;
+                    if (bc == 2) J(c, c) = -wA;
+                }
+            } else if (bc == 3 || bc == 4) {
+                br[0] = wA * (uh[0] - u[0]);
+                J(0, 20) = wA;
+                J(0, 0) = -wA;
+                for (int i = 1; i < 4; ++i) {
+                    br[i] = wA * uh[i];
+                    J(i, 20 + i) = wA;
+                }
+                if (bc == 3) {
+                    const double ew = ub[4] / ub[0] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2] + ub[3] * ub[3]) / (ub[0] * ub[0]);
+                    br[4] = wA * (uh[4] - ew * uh[0]);
+                    J(4, 24) = wA;
+                    J(4, 20) = -wA * ew;
+                } else {
+                    br[4] = out[(125 + 4) * Nqf + s];
+                    for (int k = 0; k < 25; ++k) J(4, k) = out[(25 * 4 + k) * Nqf + s];
+                }
+            } else {
+                const double nn[3] = {wN[0] / wA, wN[1] / wA, wN[2] / wA};
+                br[0] = wA * (uh[0] - u[0]);
+                J(0, 20) = wA;
+                J(0, 0) = -wA;
+                for (int i = 0; i < 3; ++i) {
+                    double t = uh[1 + i];
+                    for (int j = 0; j < 3; ++j) {
+                        const double pij = (i == j ? 1.0 : 0.0) - nn[i] * nn[j];
+                        t -= pij * u[1 + j];
+                        J(1 + i, 1 + j) = -wA * pij;
+                    }
+                    br[1 + i] = wA * t;
+                    J(1 + i, 21 + i) = wA;
+                }
+                br[4] = wA * (uh[4] - u[4]);
+                J(4, 24) = wA;
+                J(4, 4) = -wA;
+            }
+            for (int c = 0; c < 5; ++c) out[(130 + c) * Nqf + s] = br[c];
         }
     }
 }
@@ -592,9 +649,10 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
 }
 
 // Trace rows of local face lf: [C | D | R_uh] rows of this element's side, one
-// workgroup per (face, element).  Only the columns of the face's own nodes (C,
-// not on a Dirichlet face), of the face's trace block (D) and the residual
-// column are nonzero.  A table maps every column once to its basis function (or
+// workgroup per (face, element): the numerical flux on an interior face, the
+// boundary residual on a boundary face.  Only the columns of the face's own
+// nodes (C), of the face's trace block (D) and the residual column are
+// nonzero.  A table maps every column once to its basis function (or
 // to zero); each pass forms, for kTR rows (c, a), the weights
 // w(slot, s) = coefficient(c, slot)(s) mu_a(s) at the face's Gauss points, so
 // that a nonzero entry is one dot product over the Gauss points with phi_k(s)
@@ -625,7 +683,6 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
     const int pf1 = sPf[lf] + 1, nqf1 = pf1 + 1, Nfp = pf1 * pf1, Nqf = sNqf[lf];
     const int F = dm.elem_face[6 * e + lf], bc = dm.face_bc[F];
     const double *fb = qpe + sFbase[lf];
-    const double *fgl = dm.fgeo + dm.fgeo_off[6 * e + lf];
     double *Et = E + (int64_t)(n + toff[lf]) * ld;
     const int nrow = 5 * Nfp;
     // element basis phi_k and trace basis mu_b at the face's Gauss points
@@ -640,7 +697,7 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
         if (col < n) {
             const int sblk = col / Np, k = col % Np;
             int ka0, ka1;
-            if (!bc && on_face(k, p1, lf, ka0, ka1)) {
+            if (on_face(k, p1, lf, ka0, ka1)) {
                 const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
                 code = (slot << 8) | (ka0 + p1 * ka1);
             }
@@ -669,8 +726,7 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
                     const int slot = t / Nqf, sq = t % Nqf;
                     double k;
                     if (slot == 25) k = fb[(int64_t)((bc ? 130 : 125) + cc) * Nqf + sq];
-                    else if (bc) k = (slot == 20 + cc) ? fgl[3 * Nqf + sq] : 0.0;
-                    else k = fb[(int64_t)(25 * cc + slot) * Nqf + sq];
+                    else k = fb[(int64_t)((bc ? 140 : 0) + 25 * cc + slot) * Nqf + sq];
                     sK[slot][sq] = k;
                 }
                 c_loaded = cc;

@@ -42,7 +42,7 @@ class HDGError(RuntimeError):
 
 class _MeshDesc(ctypes.Structure):
     _fields_ = [("n_elem", _i), ("n_face", _i), ("n_vert", _i), ("vert_xyz", _vp), ("elem_vert", _vp),
-                ("elem_face", _vp), ("face_elem", _vp), ("face_bc", _vp), ("elem_p", _vp)]
+                ("elem_face", _vp), ("face_elem", _vp), ("face_bc", _vp), ("elem_p", _vp), ("elem_geom", _vp)]
 
 
 class _Phys(ctypes.Structure):
@@ -161,9 +161,13 @@ class Context:
             fe=np.ascontiguousarray(mesh.face_elem, dtype=np.int32),
             bc=np.ascontiguousarray(mesh.face_bc, dtype=np.int8),
             p=np.ascontiguousarray(mesh.elem_p, dtype=np.int8))
+        geom = getattr(mesh, "elem_geom", None)
+        if geom is not None:
+            self._keep["geom"] = np.ascontiguousarray(geom, dtype=np.float64).reshape(mesh.n_elem, 27, 3)
         k = self._keep
         desc = _MeshDesc(mesh.n_elem, mesh.n_face, mesh.n_vert, k["vert"].ctypes.data, k["ev"].ctypes.data,
-                         k["ef"].ctypes.data, k["fe"].ctypes.data, k["bc"].ctypes.data, k["p"].ctypes.data)
+                         k["ef"].ctypes.data, k["fe"].ctypes.data, k["bc"].ctypes.data, k["p"].ctypes.data,
+                         k["geom"].ctypes.data if geom is not None else None)
         w = wl_or_phys
         phys = _Phys(w.gamma, w.prandtl, w.reynolds, w.mach, w.tau, w.dt, w.alpha, int(w.visc_law))
         torch.cuda.init()

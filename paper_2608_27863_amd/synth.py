@@ -55,8 +55,9 @@ class Mesh:
     the global faces on local sides -x,+x,-y,+y,-z,+z; face_elem[F] =
     [[elem, local face] of side 0, [elem, local face] of side 1], side 1 is
     [-1, -1] on a boundary face.  Side 0 is the element the face normal points
-    out of.  face_bc is 0 for interior/periodic faces, 1 for Dirichlet-state
-    boundary faces.
+    out of.  face_bc is 0 for interior/periodic faces, else the boundary type
+    (1 prescribed state, 2 extrapolated, 3 isothermal wall, 4 adiabatic wall,
+    5 symmetry; box_mesh marks every non-periodic side 1).
     """
 
     vert_xyz: np.ndarray   # [n_vert, 3] float64
@@ -66,6 +67,7 @@ class Mesh:
     face_bc: np.ndarray    # [n_face] int8
     elem_p: np.ndarray     # [n_elem] int8
     shape: tuple
+    elem_geom: Optional[np.ndarray] = None  # [n_elem, 27, 3] curved geometry nodes, or None (trilinear)
 
     @property
     def n_elem(self) -> int:
@@ -124,14 +126,18 @@ def box_mesh(n: tuple, lengths=(2 * math.pi,) * 3, periodic=(True, True, True),
     vert[ids, 2] = xs[2][kk]
     if perturb > 0.0:
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
-        disp = rng.uniform(-1.0, 1.0, size=(nx, ny + 1, nz, 3))
-        if periodic[1]:
-            disp = disp[:, :ny, :, :]
+        if periodic[0] and periodic[2]:
+            disp = rng.uniform(-1.0, 1.0, size=(nx, ny + 1, nz, 3))
+            if periodic[1]:
+                disp = disp[:, :ny, :, :]
+        else:  # walls across x or z too: one draw per vertex of the box
+            disp = rng.uniform(-1.0, 1.0, size=(nx + 1, ny + 1, nz + 1, 3))
+        dims3 = (nx, ny, nz)
         for v in range(nv):
             i, j, k = ii[v], jj[v], kk[v]
-            if not periodic[1] and (j == 0 or j == ny):
+            if any(not periodic[a] and idx in (0, dims3[a]) for a, idx in enumerate((i, j, k))):
                 continue
-            di = disp[i % nx, (j % ny) if periodic[1] else j, k % nz]
+            di = disp[tuple(idx % dims3[a] if periodic[a] else idx for a, idx in enumerate((i, j, k)))]
             hloc = np.empty(3)
             for a, (idx, nn) in enumerate(((i, nx), (j, ny), (k, nz))):
                 if periodic[a]:
@@ -216,9 +222,25 @@ def group_by_degree(mesh: Mesh) -> Mesh:
         ok = e >= 0
         e[ok] = inv[e[ok]]
         fe[:, side, 0] = e
-    return dataclasses.replace(mesh, elem_vert=np.ascontiguousarray(mesh.elem_vert[perm]),
+    geom = None if mesh.elem_geom is None else np.ascontiguousarray(mesh.elem_geom[perm])
+    return dataclasses.replace(mesh, elem_geom=geom, elem_vert=np.ascontiguousarray(mesh.elem_vert[perm]),
                                elem_face=np.ascontiguousarray(mesh.elem_face[perm]),
                                face_elem=fe, elem_p=np.ascontiguousarray(mesh.elem_p[perm]))
+
+
+def set_boundary_types(mesh: Mesh, types: dict) -> Mesh:
+    """The same mesh with the boundary type of each one-sided face chosen by the
+    side of the box it lies on: types[(axis, side)] for axis 0..2 and side 0
+    (low) or 1 (high); unlisted sides keep their type."""
+    bc = mesh.face_bc.copy()
+    for F in range(mesh.n_face):
+        if mesh.face_elem[F, 1, 0] >= 0:
+            continue
+        lf = int(mesh.face_elem[F, 0, 1])
+        key = (lf // 2, lf % 2)
+        if key in types:
+            bc[F] = types[key]
+    return dataclasses.replace(mesh, face_bc=bc)
 
 
 def _trilinear(X8: np.ndarray, xi: np.ndarray) -> np.ndarray:
@@ -233,13 +255,50 @@ def _trilinear(X8: np.ndarray, xi: np.ndarray) -> np.ndarray:
     return out
 
 
+def _triquadratic(X27: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """Map reference points xi [..., 3] through 27 nodes (tensor order, at
+    reference coordinates -1, 0, 1)."""
+    def lq(t):
+        return [0.5 * t * (t - 1.0), 1.0 - t * t, 0.5 * t * (t + 1.0)]
+    L = [lq(xi[..., d]) for d in range(3)]
+    out = np.zeros(xi.shape[:-1] + (3,))
+    for c in range(3):
+        for b in range(3):
+            for a in range(3):
+                out += (L[0][a] * L[1][b] * L[2][c])[..., None] * X27[a + 3 * (b + 3 * c)]
+    return out
+
+
+def _map(mesh: Mesh, e: int, xi: np.ndarray) -> np.ndarray:
+    if mesh.elem_geom is not None:
+        return _triquadratic(np.asarray(mesh.elem_geom[e]), xi)
+    return _trilinear(mesh.vert_xyz[mesh.elem_vert[e]], xi)
+
+
+def curve_mesh(mesh: Mesh, amp: float) -> Mesh:
+    """The same mesh with curved (triquadratic) elements: the 27 nodes of each
+    element are its straight (trilinear) node positions moved by the smooth
+    displacement amp * (sin y sin z, sin z sin x, sin x sin y), which is
+    2 pi-periodic, so shared and periodic faces stay conforming."""
+    r = np.array([-1.0, 0.0, 1.0])
+    Z, Y, X = np.meshgrid(r, r, r, indexing="ij")
+    xi = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=-1)
+    geom = np.zeros((mesh.n_elem, 27, 3))
+    for e in range(mesh.n_elem):
+        x = _trilinear(mesh.vert_xyz[mesh.elem_vert[e]], xi)
+        d = np.stack([np.sin(x[:, 1]) * np.sin(x[:, 2]), np.sin(x[:, 2]) * np.sin(x[:, 0]),
+                      np.sin(x[:, 0]) * np.sin(x[:, 1])], axis=-1)
+        geom[e] = x + amp * d
+    return dataclasses.replace(mesh, elem_geom=geom)
+
+
 def element_node_xyz(mesh: Mesh, e: int) -> np.ndarray:
     """[N_p, 3] node positions of element e, tensor order x fastest."""
     p = int(mesh.elem_p[e])
     r = gll_points(p)
     Z, Y, X = np.meshgrid(r, r, r, indexing="ij")
     xi = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=-1)
-    return _trilinear(mesh.vert_xyz[mesh.elem_vert[e]], xi)
+    return _map(mesh, e, xi)
 
 
 def face_node_xyz(mesh: Mesh, F: int) -> np.ndarray:
@@ -255,7 +314,7 @@ def face_node_xyz(mesh: Mesh, F: int) -> np.ndarray:
     xi[:, d] = 1.0 if s else -1.0
     xi[:, t[0]] = A0.ravel()
     xi[:, t[1]] = A1.ravel()
-    return _trilinear(mesh.vert_xyz[mesh.elem_vert[e]], xi)
+    return _map(mesh, e, xi)
 
 
 # ------------------------------------------------------------------ states
@@ -312,7 +371,7 @@ class Workload:
     Un: np.ndarray         # packed [sum_e 5 N_p]
     Uhat: np.ndarray       # packed [sum_F 5 N_fp]   layout [F][c][node]
     nu: np.ndarray         # packed [sum_e N_p]
-    Ub: np.ndarray         # packed like Uhat; boundary state on Dirichlet faces
+    Ub: np.ndarray         # packed like Uhat; prescribed boundary state on boundary faces
     x: np.ndarray          # seeded unit-norm trace vector (matvec input)
     gmres_m: int
     seed: int

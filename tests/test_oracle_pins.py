@@ -148,8 +148,7 @@ def test_generator_tgv_kinetic_energy():
 def test_volume_and_mass_partition():
     wl = _wl(n=2, p=2, perturb=0.15)
     m = wl.mesh
-    vols = [O.lib().hdgref_element_volume(2, O._p(O._f64(m.vert_xyz[m.elem_vert[e]].ravel())))
-            for e in range(m.n_elem)]
+    vols = [O.element_volume(m, e) for e in range(m.n_elem)]
     assert abs(sum(vols) - (2 * math.pi) ** 3) < 1e-10
     E = O.element_system(wl, 3)
     Np = 27
