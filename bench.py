@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--matvec-reps", type=int, default=100)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default 128-row update tiles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU's partition only (--gpus {args.gpus} requested); "
@@ -264,6 +265,12 @@ def main():
             step()
             torch.cuda.synchronize()
             print(f"[bench] {label}: warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    # tile shape of the LU's trailing update, per size of system, chosen by measurement
+    tiles = None
+    if not args.no_autotune:
+        table = pipeline.autotune_update_tiles(st, log=lambda m: print(m, file=sys.stderr, flush=True))
+        tiles = {str(k): {"rows": v[0], "ms": {str(r): t for r, t in v[1].items()}} for k, v in table.items()}
 
     # ---------------------------------------------------------------- FP64 path
     step = stepper(st)
@@ -358,7 +365,8 @@ def main():
                    "chunk": chunk or ne, "batches": [c for _, c in st.chunks], "gmres_iterations": st.m,
                    "schwarz": "element-block, " + ("FP32 inverses" if big else "FP64"), "precision": "FP64",
                    "step": f"residual+Jacobian, condensation, assembly, Schwarz set-up, GMRES({st.m}), recovery",
-                   "value_is": "N_e / median(T(hdg_condense, all chunks) + T(hdg_assemble_trace))"},
+                   "value_is": "N_e / median(T(hdg_condense, all chunks) + T(hdg_assemble_trace))",
+                   "update_tiles": tiles},
         "step_elements_per_s": ne / (r64["ms_step"] * 1e-3),
         "condense_ms": r64["condense_ms"],
         "condense_assemble_ms": r64["cond_asm_ms"],

@@ -202,6 +202,18 @@ int hdg_local_residual_jacobian(hdg_ctx *ctx, int e0, int ne,
                                 double *E, void *work, size_t work_bytes, void *stream);
 
 /*
+ * Tile shape of the trailing update of the blocked LU (the dominant kernel of
+ * hdg_condense and of the Schwarz inversion), per size of system: systems with
+ * n pivot columns (n = 20 N_p for element systems; n = 0 sets the default for
+ * every size) use tiles of tile_rows x 128 (tile_rows 128 or 256; default
+ * 128).  Chosen by measurement (the Python pipeline's autotuner times both on
+ * the device).  A chunk mixing sizes uses the setting of its largest n.
+ * hdg_get_update_tile returns the rows in effect for n.
+ */
+int hdg_set_update_tile(hdg_ctx *ctx, int n, int tile_rows);
+int hdg_get_update_tile(const hdg_ctx *ctx, int n);
+
+/*
  * Static condensation (eqs. local-elimination, schur-trace) of elements
  * e0 .. e0+ne-1.  E (element e0's system first) is overwritten:
  *  HDG_FP64: partial LU with partial pivoting of the first n columns of E

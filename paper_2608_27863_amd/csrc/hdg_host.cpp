@@ -823,6 +823,20 @@ static int newton_enqueue(hdg_ctx *ctx, const hdg_newton_args *a, void *stream) 
     return HDG_OK;
 }
 
+int hdg_set_update_tile(hdg_ctx *ctx, int n, int tile_rows) {
+    if (!ctx || n < 0 || (tile_rows != 128 && tile_rows != 256)) return HDG_ERR_INVALID_ARGUMENT;
+    ctx->update_tile[n] = tile_rows;
+    return HDG_OK;
+}
+
+int hdg_get_update_tile(const hdg_ctx *ctx, int n) {
+    if (!ctx || n < 0) return HDG_ERR_INVALID_ARGUMENT;
+    auto it = ctx->update_tile.find(n);
+    if (it != ctx->update_tile.end()) return it->second;
+    it = ctx->update_tile.find(0);
+    return it != ctx->update_tile.end() ? it->second : 128;
+}
+
 int hdg_newton_step(hdg_ctx *ctx, const hdg_newton_args *args, void *stream) {
     const int rc = newton_check(ctx, args);
     if (rc) return rc;

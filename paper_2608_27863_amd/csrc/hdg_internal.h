@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <vector>
 
 #include "../../include/hdg.h"
@@ -109,6 +110,7 @@ struct hdg_ctx {
     std::vector<int> bsr_row_ptr, bsr_col;
     hdg::DevMesh dm{};
     std::vector<void *> allocations;  // device buffers owned by the context
+    std::map<int, int> update_tile;   // n (0: every n) -> rows of the trailing-update tile (128 or 256)
 };
 
 namespace hdg {

@@ -1089,8 +1089,9 @@ __global__ void __launch_bounds__(256) k_blocku(DevMesh dm, SysDesc sd, int e0, 
 //              k0+min(CW, n_e-k0) (CW > 0) or to ncols  (the LU's trailing update)
 //   kRangeFwd: rows [k0+K, n), columns [n, ncols)  (forward substitution of the
 //              right-hand columns)
-// 128 x 128 tile per workgroup, K in chunks of 16 (FP64) or 32 (FP32) values
-// double-buffered through LDS, matrix cores; C is read before the K loop.
+// TM x 128 tile per workgroup (TM = 128 or 256), K in chunks of 16 (FP64) or
+// 32 (FP32) values double-buffered through LDS, matrix cores; C is read before
+// the K loop.
 constexpr int kRangeLU = 0, kRangeFwd = 1;
 constexpr int kFold = 128;  // FP32 products are folded into C every kFold values of K
 constexpr int kTM = 128, kTN = 128;
@@ -1103,10 +1104,19 @@ template <typename T> struct UpdCfg {
     static constexpr int KPQ = 256 / LPK; // k-rows of B per load step
 };
 
-template <typename T, int TAG, int RANGE>
-__global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int KW, int CB,
-                                                   int CW, int tiles_m, int tiles_n, T *__restrict__ Ebase) {
+// TM = 128 (256 threads, two workgroups per CU) or 256 (512 threads, one
+// workgroup per CU): each wave owns a 64 x 64 sub-tile either way; the taller
+// tile reads its B chunk once for twice the rows.
+template <typename T, int TAG, int RANGE, int TM = kTM>
+__global__ void __launch_bounds__(2 * TM, 256 / TM) k_update(DevMesh dm, SysDesc sd, int e0, int ne, int k0, int KW,
+                                                             int CB, int CW, int tiles_m, int tiles_n,
+                                                             T *__restrict__ Ebase) {
     typedef UpdCfg<T> C;
+    constexpr int NT = 2 * TM;                 // threads
+    constexpr int RQ = NT / 8;                 // A-chunk rows per load step
+    constexpr int KPQ = NT / C::LPK;           // B-chunk k-rows per load step
+    constexpr int QB = C::KC / KPQ;            // B load steps per chunk
+    static_assert(4 * RQ == TM && QB * KPQ == C::KC && QB >= 1, "update tile shape");
     typedef typename MF<T>::v16 v16;
     typedef typename MF<T>::acc_t acc_t;
     int el, t;
@@ -1124,14 +1134,14 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     } else {
         rbeg = k0 + K; rend = dd.n; cbeg = dd.n; cend = dd.ncols;
     }
-    const int r0 = rbeg + (t / tiles_n) * kTM;
+    const int r0 = rbeg + (t / tiles_n) * TM;
     const int c0 = cbeg + (t % tiles_n) * kTN;
     if (r0 >= rend || c0 >= cend) return;
     T *E = Ebase + (sd.off[e] - sd.off[e0]);
     const int64_t ld = dd.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;  // wave sub-tile origin
-    __shared__ __attribute__((aligned(16))) T sA[2][kTM][C::SA];
+    __shared__ __attribute__((aligned(16))) T sA[2][TM][C::SA];
     __shared__ __attribute__((aligned(16))) T sB[2][C::KC][C::SB];
     // chunk loads with 16-byte accesses: A chunk (128 rows x KC k): 8 lanes per
     // 128-byte row segment, rows 32q + tid/8; B chunk (KC k x 128 columns): LPK
@@ -1145,7 +1155,7 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     bool aok[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int row = r0 + 32 * q + ar;
+        const int row = r0 + RQ * q + ar;
         aok[q] = row < rend;
         arow[q] = E + (int64_t)min(row, rend - 1) * ld + k0;
     }
@@ -1159,8 +1169,8 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
 #pragma unroll
         for (int q = 0; q < 4; ++q) ra[q] = *(const v16 *)(arow[q] + gkc);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int gk2 = kc + C::KPQ * q + bk;
+        for (int q = 0; q < QB; ++q) {
+            const int gk2 = kc + KPQ * q + bk;
             rb[q] = *(const v16 *)(E + (int64_t)(k0 + min(gk2, K - 1)) * ld + bcolc);
         }
     };
@@ -1168,16 +1178,19 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
         const int gk = kc + ak;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            v16 a, b;
-            const int gk2 = kc + C::KPQ * q + bk;
+            v16 a;
+#pragma unroll
+            for (int i = 0; i < C::V; ++i) a[i] = (aok[q] && gk + i < K) ? ra[q][i] : T(0);
+            *(v16 *)&sA[buf][RQ * q + ar][ak] = (sizeof(T) == 8) ? -a : a;
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            v16 b;
+            const int gk2 = kc + KPQ * q + bk;
             const bool k2ok = gk2 < K;
 #pragma unroll
-            for (int i = 0; i < C::V; ++i) {
-                a[i] = (aok[q] && gk + i < K) ? ra[q][i] : T(0);
-                b[i] = (k2ok && bcol + i < cend) ? rb[q][i] : T(0);
-            }
-            *(v16 *)&sA[buf][32 * q + ar][ak] = (sizeof(T) == 8) ? -a : a;
-            *(v16 *)&sB[buf][C::KPQ * q + bk][bc] = b;
+            for (int i = 0; i < C::V; ++i) b[i] = (k2ok && bcol + i < cend) ? rb[q][i] : T(0);
+            *(v16 *)&sB[buf][KPQ * q + bk][bc] = b;
         }
     };
     // C is read at the start so that its loads overlap the operand loads.  FP64:
@@ -1188,7 +1201,7 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
     constexpr bool kOntoC = sizeof(T) == 8;
     acc_t acc[4][4];
     acc_t cpre[kOntoC ? 1 : 4][4];
-    const bool full = (r0 + kTM <= rend) && (c0 + kTN <= cend);
+    const bool full = (r0 + TM <= rend) && (c0 + kTN <= cend);
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -1207,7 +1220,7 @@ __global__ void __launch_bounds__(256, 2) k_update(DevMesh dm, SysDesc sd, int e
                 }
             }
         }
-    v16 ra[4], rb[4];
+    v16 ra[4], rb[QB];
     load_chunk(0, ra, rb);
     store_chunk(0, 0, ra, rb);
     __syncthreads();
@@ -1709,6 +1722,15 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
 
 }  // namespace
 
+// Rows of the trailing-update tile for systems with n pivot columns: the
+// context's setting for that n (hdg_set_update_tile), else for every n, else 128.
+static int update_tile_rows(const hdg_ctx *ctx, int n) {
+    auto it = ctx->update_tile.find(n);
+    if (it != ctx->update_tile.end()) return it->second;
+    it = ctx->update_tile.find(0);
+    return it != ctx->update_tile.end() ? it->second : kTM;
+}
+
 // Blocked LU of the systems e0..e0+ne-1 described by sd (bordered: trace rows
 // included when maxf_rows > 0).  ws: per-element workspace of a pair of
 // 128-column blocks, or with `persist` one per block (ws strides hold all of
@@ -1735,11 +1757,16 @@ static int run_lu(const hdg_ctx *ctx, const SysDesc &sd, int e0, int ne, T *E, i
         wb.i += (int64_t)slot * kWsInt;
         return wb;
     };
+    const int TMr = update_tile_rows(ctx, maxn);
     auto update = [&](int k0, int KW, int CB, int CW, int rows, int cols) {
         if (rows <= 0 || cols <= 0) return;
-        const int tm = (rows + kTM - 1) / kTM, tn = (cols + kTN - 1) / kTN;
-        hipLaunchKernelGGL((k_update<T, TAG, kRangeLU>), dim3(xcd_grid(ne, tm * tn)), dim3(256), 0, s, dm, sd, e0, ne,
-                           k0, KW, CB, CW, tm, tn, E);
+        const int tm = (rows + TMr - 1) / TMr, tn = (cols + kTN - 1) / kTN;
+        if (TMr == 256)
+            hipLaunchKernelGGL((k_update<T, TAG, kRangeLU, 256>), dim3(xcd_grid(ne, tm * tn)), dim3(512), 0, s, dm, sd,
+                               e0, ne, k0, KW, CB, CW, tm, tn, E);
+        else
+            hipLaunchKernelGGL((k_update<T, TAG, kRangeLU>), dim3(xcd_grid(ne, tm * tn)), dim3(256), 0, s, dm, sd, e0,
+                               ne, k0, KW, CB, CW, tm, tn, E);
     };
     auto blocku = [&](auto mode, int k0, const WS<T> &wb, int CB, int CW, int cols) {
         if (cols <= 0) return;
@@ -1861,9 +1888,14 @@ static void run_forward_solve(const hdg_ctx *ctx, const SysDesc &sd, int e0, int
                                K0 + kNBO, 1, 0, 0, tiles, E, block_ws(ws, K0 + kNBO));
         const int rows = maxn - K0 - 2 * kNBO;
         if (rows > 0) {
-            const int tm = (rows + kTM - 1) / kTM;
-            hipLaunchKernelGGL((k_update<T, TAG, kRangeFwd>), dim3(xcd_grid(ne, tm * tn)), dim3(256), 0, s, dm, sd,
-                               e0, ne, K0, 2 * kNBO, 0, 0, tm, tn, E);
+            const int TMr = update_tile_rows(ctx, maxn);
+            const int tm = (rows + TMr - 1) / TMr;
+            if (TMr == 256)
+                hipLaunchKernelGGL((k_update<T, TAG, kRangeFwd, 256>), dim3(xcd_grid(ne, tm * tn)), dim3(512), 0, s, dm,
+                                   sd, e0, ne, K0, 2 * kNBO, 0, 0, tm, tn, E);
+            else
+                hipLaunchKernelGGL((k_update<T, TAG, kRangeFwd>), dim3(xcd_grid(ne, tm * tn)), dim3(256), 0, s, dm, sd,
+                                   e0, ne, K0, 2 * kNBO, 0, 0, tm, tn, E);
         }
     }
 }

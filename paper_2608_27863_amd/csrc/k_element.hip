@@ -462,9 +462,26 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
     __shared__ double sV[2][p1 * p1 * p1][nq];   // y stage of one i1 slice
     __shared__ double sF[kSF];                   // face terms / trace-column blocks
     __shared__ double sG[kSG];                   // first stage of the 2-D contractions
+    __shared__ unsigned char sNm[Np];            // faces each node lies on (bit lf)
+    __shared__ unsigned char sNa[6][Np];         // its face-local index a0 p1 + a1 there
     for (int t = tid; t < p1 * nq; t += blockDim.x) {
         sL[t / nq][t % nq] = dm.tbl[tbl_L(p, p, t / nq, t % nq)];
         sD[t / nq][t % nq] = dm.tbl[tbl_D(p, t / nq, t % nq)];
+    }
+    for (int i = tid; i < Np; i += blockDim.x) {
+        const int idx[3] = {i % p1, (i / p1) % p1, i / (p1 * p1)};
+        unsigned m = 0;
+        for (int lf = 0; lf < 6; ++lf) {
+            const int d = lf >> 1;
+            if (idx[d] == ((lf & 1) ? p : 0)) {
+                m |= 1u << lf;
+                const int a0 = (d == 0) ? idx[1] : idx[0], a1 = (d == 2) ? idx[1] : idx[2];
+                sNa[lf][i] = (unsigned char)(a0 * p1 + a1);
+            } else {
+                sNa[lf][i] = 0;
+            }
+        }
+        sNm[i] = (unsigned char)m;
     }
     load_face_tables(dm, e, p, Nq, sLf, sMf, sPf, sNqf, sFbase);
     __syncthreads();
@@ -521,10 +538,13 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
                 for (int g3 = 0; g3 < nq; ++g3)
                     v += (sL[i3][g3] * sV[0][vq][g3] + sD[i3][g3] * sV[1][vq][g3]) * sL[k3][g3];
                 if (faces) {
-                    for (int lf = 0; lf < 6; ++lf) {
-                        int a0, a1, b0, b1;
-                        if (face_idx(i1, i2, i3, lf, a0, a1) && face_idx(k1, k2, k3, lf, b0, b1))
-                            v += sF[lf * p1 * p1 * p1 * p1 + ((a0 * p1 + a1) * p1 + b0) * p1 + b1];
+                    // face terms of the faces that both node i and node k lie on (ascending lf)
+                    const int irow = i1 + p1 * (i2 + p1 * i3);
+                    unsigned m = sNm[irow] & sNm[k];
+                    while (m) {
+                        const int lf = __builtin_ctz(m);
+                        m &= m - 1;
+                        v += sF[lf * p1 * p1 * p1 * p1 + sNa[lf][irow] * p1 * p1 + sNa[lf][k]];
                     }
                 }
                 Er[(int64_t)(i1 + p1 * q) * ld + sblk * Np + k] = v;

@@ -27,7 +27,8 @@ EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_
            "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior",
            "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy",
            "hdg_asm_block_apply_noalloc", "hdg_gmres_x0", "hdg_rb_guess", "hdg_rb_insert", "hdg_state_update",
-           "hdg_state_admissible", "hdg_lincomb", "hdg_residual_gather", "hdg_residual_norm", "hdg_av_field"]
+           "hdg_state_admissible", "hdg_lincomb", "hdg_residual_gather", "hdg_residual_norm", "hdg_av_field",
+           "hdg_set_update_tile", "hdg_get_update_tile"]
 
 RB_MAX = 32
 
@@ -110,6 +111,8 @@ def load_library(path: str = LIB_PATH):
     L.hdg_residual_gather.argtypes = [_vp, _i, _i, _vp, _vp, ctypes.c_size_t, _vp]
     L.hdg_residual_norm.argtypes = [_vp, _vp, ctypes.c_size_t, _vp, _vp]
     L.hdg_av_field.argtypes = [_vp, ctypes.POINTER(_AvParams), _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.hdg_set_update_tile.argtypes = [_vp, _i, _i]
+    L.hdg_get_update_tile.argtypes = [_vp, _i]
     for name in EXPORTS:
         if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length", "hdg_graph_destroy"):
             getattr(L, name).restype = _i
@@ -373,6 +376,15 @@ class Context:
                                  _ptr(nu, f64, nn, "nu"), _ptr(work, None, None, "work"),
                                  work.numel() * work.element_size(), _stream(stream))
         _check(rc, "hdg_av_field")
+
+    def hdg_set_update_tile(self, n, tile_rows):
+        _check(self.L.hdg_set_update_tile(self.h, int(n), int(tile_rows)), "hdg_set_update_tile")
+
+    def hdg_get_update_tile(self, n):
+        rc = self.L.hdg_get_update_tile(self.h, int(n))
+        if rc < 0:
+            _check(rc, "hdg_get_update_tile")
+        return rc
 
     # ------------------------------------------------------- whole step
     def newton_args(self, st):

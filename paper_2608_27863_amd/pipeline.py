@@ -272,3 +272,74 @@ class DirkStepper:
             ctx.hdg_lincomb([st.U], [1.0], self.stages[i], stream)
         ctx.hdg_lincomb([self.Un] + self.stages, [1.0 - sum(e)] + list(e), st.U, stream)
         return hists
+
+
+def autotune_update_tiles(step, candidates=(128, 256), reps=2, schwarz=True, log=None):
+    """Choose the trailing-update tile of the blocked LU by measurement on the
+    device: for each size of element system in the step (n = 20 N_p), time
+    hdg_condense of that size's chunks with each candidate tile height (the
+    element systems are rebuilt by hdg_local_residual_jacobian before every
+    timed run, since condensation overwrites them), keep the fastest in the
+    context (hdg_set_update_tile) and return the table {n: (rows, {rows: ms})}.
+    With `schwarz`, the Schwarz inversion systems (size f rounded up to a
+    multiple of 4) are tuned on hdg_asm_setup after one whole step."""
+    import torch
+    ctx = step.ctx
+    s = torch.cuda.current_stream()
+    sizes = {}
+    for e0, n in step.chunks:
+        sizes.setdefault(int(ctx.layout["elem_n"][e0]), []).append((e0, n))
+    table = {}
+
+    def timed(fn):
+        best = None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            fn()
+            b.record(s)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    for nsz, chunks in sorted(sizes.items()):
+        times = {}
+        for rows in candidates:
+            ctx.hdg_set_update_tile(nsz, rows)
+
+            def run():
+                for e0, n in chunks:
+                    ctx.hdg_condense(step.prec, step.refine, e0, n, step.E_chunk(e0, n), step.SK, step.info,
+                                     step.cond_work)
+            ms = None
+            for _ in range(reps):
+                for e0, n in chunks:
+                    ctx.hdg_local_residual_jacobian(e0, n, step.Q, step.U, step.Un, step.Uhat, step.nu,
+                                                    step.Ub if step.wl.mesh.face_bc.any() else None,
+                                                    step.E_chunk(e0, n), step.qp_work)
+                t = timed(run)
+                ms = t if ms is None else min(ms, t)
+            times[rows] = ms
+        best = min(times, key=times.get)
+        ctx.hdg_set_update_tile(nsz, best)
+        table[nsz] = (best, times)
+        if log:
+            log(f"[autotune] element systems n={nsz}: " + ", ".join(f"{r} rows {t:.2f} ms" for r, t in times.items())
+                + f" -> {best}")
+    if schwarz:
+        step.run_calls()
+        torch.cuda.synchronize()
+        maxf = int(max(ctx.layout["elem_f"]))
+        m = (maxf + 3) & ~3  # size of the Schwarz inversion systems
+        times = {}
+        for rows in candidates:
+            ctx.hdg_set_update_tile(m, rows)
+            times[rows] = timed(lambda: step.asm_setup())
+        best = min(times, key=times.get)
+        ctx.hdg_set_update_tile(m, best)
+        table[m] = (best, times)
+        if log:
+            log(f"[autotune] Schwarz systems m={m}: " + ", ".join(f"{r} rows {t:.2f} ms" for r, t in times.items())
+                + f" -> {best}")
+    return table
