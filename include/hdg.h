@@ -87,9 +87,14 @@ typedef enum {
 /* Arithmetic of the element condensation and of the Schwarz blocks. */
 typedef enum {
     HDG_FP64 = 0,   /* FP64 throughout                                          */
-    HDG_MIXED = 1   /* FP32 LU / triangular solves with FP32 accumulation,
+    HDG_MIXED = 1,  /* FP32 LU / triangular solves with FP32 accumulation,
                        FP64-residual iterative refinement of A^{-1}[B|R_qu],
                        FP64 Schur product; Schwarz inverses stored in FP32     */
+    HDG_MIXED_FAST = 2 /* hdg_condense only (and the recovery after it): the whole
+                       bordered system factored in FP32, the Schur complement
+                       formed by the FP32 trailing updates with FP32
+                       accumulation, no refinement.  Error about cond(A) u_32:
+                       reported beside HDG_MIXED, not accurate to 1e-10        */
 } hdg_precision;
 
 /* Mesh: conforming hexahedra, all elements identically oriented (every face is
@@ -221,6 +226,9 @@ int hdg_get_update_tile(const hdg_ctx *ctx, int n);
  *    trace rows and the [B | R_qu] columns.  Afterwards rows 0..n-1 hold U (upper
  *    triangle of the n x n block) and L^{-1} P [B | R_qu]; rows n.. hold
  *    [S^K | -g^K].
+ *  HDG_MIXED_FAST: as HDG_FP64 but in FP32 (an FP32 copy of the systems in the
+ *    workspace); S^K and g^K carry the FP32 rounding; rows 0..n-1 of E are then
+ *    overwritten with the FP32 factors converted to FP64 (for the recovery).
  *  HDG_MIXED: A is factorised in FP32 in the workspace, X = A^{-1}[B | R_qu] is
  *    refined `refine_steps` (>= 1) times with FP64 residuals [B|R_qu] - A X, S^K
  *    and g^K are formed with FP64 products; X is then stored in place of
@@ -405,7 +413,8 @@ int hdg_residual_norm(hdg_ctx *ctx, void *work, size_t work_bytes, double *norms
 /*
  * Interior recovery (eq. local-elimination): for elements e0 .. e0+ne-1,
  * d(Q,U)^K = -A^{-1} (R_qu + B dUh^K), from E as left by hdg_condense with the
- * same `prec` (HDG_FP64: back substitution with U; HDG_MIXED: -(x_r + X_B dUh)).
+ * same `prec` (HDG_FP64 and HDG_MIXED_FAST: back substitution with U;
+ * HDG_MIXED: -(x_r + X_B dUh)).
  * dQU is the packed node array (all elements).
  */
 int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E,

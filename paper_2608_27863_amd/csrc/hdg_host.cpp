@@ -579,7 +579,8 @@ static bool chunk_ok(const hdg_ctx *ctx, int e0, int ne) {
 static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
 int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, size_t *bytes) {
-    if (!ctx || !bytes || (prec != HDG_FP64 && prec != HDG_MIXED)) return HDG_ERR_INVALID_ARGUMENT;
+    if (!ctx || !bytes || (prec != HDG_FP64 && prec != HDG_MIXED && !(op == 1 && prec == HDG_MIXED_FAST)))
+        return HDG_ERR_INVALID_ARGUMENT;
     switch (op) {
         case 0:  // hdg_local_residual_jacobian
             if (!chunk_ok(ctx, e0, ne)) return HDG_ERR_INVALID_ARGUMENT;
@@ -587,8 +588,9 @@ int hdg_workspace_size(const hdg_ctx *ctx, int op, int prec, int e0, int ne, siz
             return HDG_OK;
         case 1:  // hdg_condense
             if (!chunk_ok(ctx, e0, ne)) return HDG_ERR_INVALID_ARGUMENT;
-            *bytes = (prec == HDG_FP64) ? round256(hdg::bordered_lu_work(ctx, ne))
-                                        : hdg::condense_mixed_work_bytes(ctx, e0, ne);
+            *bytes = (prec == HDG_FP64)    ? round256(hdg::bordered_lu_work(ctx, ne))
+                     : (prec == HDG_MIXED) ? hdg::condense_mixed_work_bytes(ctx, e0, ne)
+                                           : hdg::condense_fast_work_bytes(ctx, e0, ne);
             return HDG_OK;
         case 2: *bytes = hdg::asm_setup_work_bytes(ctx, prec); return HDG_OK;
         case 3: *bytes = hdg::asm_apply_work_bytes(ctx); return HDG_OK;
@@ -627,13 +629,15 @@ int hdg_local_residual_jacobian(hdg_ctx *ctx, int e0, int ne, const double *Q, c
 int hdg_condense(hdg_ctx *ctx, int prec, int refine_steps, int e0, int ne, double *E, double *SK, int *info,
                  void *work, size_t work_bytes, void *stream) {
     if (!chunk_ok(ctx, e0, ne) || !E || !SK || !info) return HDG_ERR_INVALID_ARGUMENT;
-    if (prec != HDG_FP64 && prec != HDG_MIXED) return HDG_ERR_INVALID_ARGUMENT;
+    if (prec != HDG_FP64 && prec != HDG_MIXED && prec != HDG_MIXED_FAST) return HDG_ERR_INVALID_ARGUMENT;
     if (prec == HDG_MIXED && (refine_steps < 1 || refine_steps > 8)) return HDG_ERR_INVALID_ARGUMENT;
     size_t need;
     hdg_workspace_size(ctx, 1, prec, e0, ne, &need);
     if (!work || work_bytes < need) return HDG_ERR_WORKSPACE;
     if (prec == HDG_FP64)
         return dev_status(hdg::launch_condense_fp64(ctx, e0, ne, E, SK, info, work, (hipStream_t)stream));
+    if (prec == HDG_MIXED_FAST)
+        return dev_status(hdg::launch_condense_fast(ctx, e0, ne, E, SK, info, work, (hipStream_t)stream));
     return dev_status(hdg::launch_condense_mixed(ctx, e0, ne, refine_steps, E, SK, info, work, (hipStream_t)stream));
 }
 
@@ -753,15 +757,18 @@ int hdg_residual_norm(hdg_ctx *ctx, void *work, size_t work_bytes, double *norms
 
 int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E, const double *dUhat,
                          double *dQU, void *stream) {
-    if (!chunk_ok(ctx, e0, ne) || !E || !dUhat || !dQU || (prec != HDG_FP64 && prec != HDG_MIXED))
+    if (!chunk_ok(ctx, e0, ne) || !E || !dUhat || !dQU ||
+        (prec != HDG_FP64 && prec != HDG_MIXED && prec != HDG_MIXED_FAST))
         return HDG_ERR_INVALID_ARGUMENT;
+    if (prec == HDG_MIXED_FAST) prec = HDG_FP64;  // E holds U and L^{-1} P [B | R_qu] in either case
     return dev_status(hdg::launch_recover(ctx, prec, e0, ne, E, dUhat, dQU, (hipStream_t)stream));
 }
 
 // ------------------------------------------------------ the whole step
 static int newton_check(hdg_ctx *ctx, const hdg_newton_args *a) {
     if (!ctx || !a) return HDG_ERR_INVALID_ARGUMENT;
-    if ((a->prec != HDG_FP64 && a->prec != HDG_MIXED) || (a->asm_prec != HDG_FP64 && a->asm_prec != HDG_MIXED))
+    if ((a->prec != HDG_FP64 && a->prec != HDG_MIXED && a->prec != HDG_MIXED_FAST) ||
+        (a->asm_prec != HDG_FP64 && a->asm_prec != HDG_MIXED))
         return HDG_ERR_INVALID_ARGUMENT;
     if (a->prec == HDG_MIXED && (a->refine_steps < 1 || a->refine_steps > 8)) return HDG_ERR_INVALID_ARGUMENT;
     if (a->gmres_m < 1 || a->gmres_m > 200) return HDG_ERR_INVALID_ARGUMENT;

@@ -123,6 +123,9 @@ int launch_condense_fp64(const hdg_ctx *ctx, int e0, int ne, double *E, double *
 int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double *E, double *SK,
                           int *info, void *work, hipStream_t s);
 size_t condense_mixed_work_bytes(const hdg_ctx *ctx, int e0, int ne);
+int launch_condense_fast(const hdg_ctx *ctx, int e0, int ne, double *E, double *SK, int *info, void *work,
+                         hipStream_t s);
+size_t condense_fast_work_bytes(const hdg_ctx *ctx, int e0, int ne);
 size_t bordered_lu_work(const hdg_ctx *ctx, int ne);
 int run_asm_inversion(const hdg_ctx *ctx, int prec, void *sys, int *info, void *work, hipStream_t s);
 int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, hipStream_t s);

@@ -1287,14 +1287,15 @@ __global__ void __launch_bounds__(2 * TM, 256 / TM) k_update(DevMesh dm, SysDesc
 
 // ------------------------------------------------------------------ extract
 // SK (column-major f x (f+1)) = [ trailing f x f block | - last column ]
-__global__ void __launch_bounds__(256) k_extract(DevMesh dm, SysDesc sd, int e0, const double *__restrict__ Ebase,
+template <typename T>
+__global__ void __launch_bounds__(256) k_extract(DevMesh dm, SysDesc sd, int e0, const T *__restrict__ Ebase,
                                                  double *__restrict__ SK) {
     const int e = e0 + blockIdx.z;
     const ElemDims dd = elem_dims(dm, sd, e);
     const int f = dd.f;
     const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;  // i: row of S, j: column (0..f)
     if (i0 >= f || j0 > f) return;
-    const double *E = Ebase + (sd.off[e] - sd.off[e0]);
+    const T *E = Ebase + (sd.off[e] - sd.off[e0]);
     double *out = SK + dm.SK_off[e];
     __shared__ double tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -1302,7 +1303,7 @@ __global__ void __launch_bounds__(256) k_extract(DevMesh dm, SysDesc sd, int e0,
         const int i = i0 + r, j = j0 + tx;
         double v = 0.0;
         if (i < f && j <= f) {
-            v = E[(int64_t)(dd.n + i) * dd.ld + dd.n + j];
+            v = (double)E[(int64_t)(dd.n + i) * dd.ld + dd.n + j];
             if (j == f) v = -v;
         }
         tile[r][tx] = v;
@@ -1843,8 +1844,8 @@ int launch_condense_fp64(const hdg_ctx *ctx, int e0, int ne, double *E, double *
                   2 * kWsInt};
     int err = run_lu<double, 0>(ctx, sd, e0, ne, E, info, ws, false, maxn, maxm, maxm + 1, maxf + 1, maxf, s);
     if (err) return err;
-    hipLaunchKernelGGL(k_extract, dim3((maxf + 1 + 31) / 32, (maxf + 31) / 32, ne), dim3(256), 0, s, ctx->dm, sd,
-                       e0, (const double *)E, SK);
+    hipLaunchKernelGGL(k_extract<double>, dim3((maxf + 1 + 31) / 32, (maxf + 31) / 32, ne), dim3(256), 0, s,
+                       ctx->dm, sd, e0, (const double *)E, SK);
     return (int)hipGetLastError();
 }
 
@@ -1953,6 +1954,55 @@ static MixedLayout mixed_layout(const hdg_ctx *ctx, int e0, int ne) {
 }
 
 size_t condense_mixed_work_bytes(const hdg_ctx *ctx, int e0, int ne) { return mixed_layout(ctx, e0, ne).total; }
+
+// ------------------------------------------------ all-FP32 variant (reported)
+// The whole bordered element system in FP32 (E_off offsets, counted in floats),
+// factored by the same blocked LU with FP32 matrix cores: its trailing updates
+// form S^K and -g^K in FP32 (no refinement, FP32 Schur products).  Afterwards
+// the interior rows (U, L^{-1} P [B | R_qu]) go back to E in FP64 for the
+// recovery.
+__global__ void __launch_bounds__(256) k_full_to32(DevMesh dm, int e0, const double *__restrict__ Ebase,
+                                                   float *__restrict__ Fbase) {
+    const int e = e0 + blockIdx.y;
+    const int64_t o = dm.E_off[e] - dm.E_off[e0], total = dm.E_off[e + 1] - dm.E_off[e];
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+        Fbase[o + i] = (float)Ebase[o + i];
+}
+__global__ void __launch_bounds__(256) k_interior_to64(DevMesh dm, int e0, const float *__restrict__ Fbase,
+                                                       double *__restrict__ Ebase) {
+    const int e = e0 + blockIdx.y;
+    const int p = dm.elem_p[e], n = 20 * (p + 1) * (p + 1) * (p + 1), f = dm.toff[7 * e + 6];
+    const int64_t o = dm.E_off[e] - dm.E_off[e0], total = (int64_t)n * e_ld(n, f);
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+        Ebase[o + i] = (double)Fbase[o + i];
+}
+
+size_t condense_fast_work_bytes(const hdg_ctx *ctx, int e0, int ne) {
+    const size_t sys = r256(sizeof(float) * (size_t)(ctx->E_off[e0 + ne] - ctx->E_off[e0]));
+    return sys + r256(2 * (sizeof(float) * (size_t)ne * kWsDbl)) + r256(2 * sizeof(int) * (size_t)ne * kWsInt);
+}
+
+int launch_condense_fast(const hdg_ctx *ctx, int e0, int ne, double *E, double *SK, int *info, void *work,
+                         hipStream_t s) {
+    int maxn, maxf, maxm = 0;
+    chunk_max(ctx, e0, ne, &maxn, &maxf);
+    for (int e = e0; e < e0 + ne; ++e) maxm = std::max(maxm, ctx->elem_n[e] + ctx->elem_f[e]);
+    char *wb = (char *)work;
+    float *F = (float *)wb;
+    const size_t sys = r256(sizeof(float) * (size_t)(ctx->E_off[e0 + ne] - ctx->E_off[e0]));
+    float *wd = (float *)(wb + sys);
+    int *wi = (int *)(wb + sys + r256(2 * (sizeof(float) * (size_t)ne * kWsDbl)));
+    const SysDesc sd{0, ctx->dm.E_off};
+    WS<float> ws{wd, wi, 2 * kWsDbl, 2 * kWsInt};
+    const dim3 grid(64, ne);
+    hipLaunchKernelGGL(k_full_to32, grid, dim3(256), 0, s, ctx->dm, e0, (const double *)E, F);
+    int err = run_lu<float, 4>(ctx, sd, e0, ne, F, info, ws, false, maxn, maxm, maxm + 1, maxf + 1, maxf, s);
+    if (err) return err;
+    hipLaunchKernelGGL(k_extract<float>, dim3((maxf + 1 + 31) / 32, (maxf + 31) / 32, ne), dim3(256), 0, s,
+                       ctx->dm, sd, e0, (const float *)F, SK);
+    hipLaunchKernelGGL(k_interior_to64, grid, dim3(256), 0, s, ctx->dm, e0, (const float *)F, E);
+    return (int)hipGetLastError();
+}
 
 int launch_condense_mixed(const hdg_ctx *ctx, int e0, int ne, int refine, double *E, double *SK, int *info,
                           void *work, hipStream_t s) {

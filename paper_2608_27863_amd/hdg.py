@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
 HDG_FP64 = 0
 HDG_MIXED = 1
+HDG_MIXED_FAST = 2  # all-FP32 condensation, reported beside HDG_MIXED
 
 LAYOUT = {"node_off": 0, "face_off": 1, "E_off": 2, "SK_off": 3, "bsr_row_ptr": 4, "bsr_col": 5,
           "bsr_val_off": 6, "asm_off": 7, "elem_n": 8, "elem_f": 9}

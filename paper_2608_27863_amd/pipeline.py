@@ -24,7 +24,8 @@ class NewtonStep:
         self.wl = wl
         self.prec = prec
         self.refine = refine_steps
-        self.asm_prec = prec if asm_prec is None else asm_prec
+        # Schwarz inverses: FP64 with the FP64 path, FP32 otherwise
+        self.asm_prec = (HDG_FP64 if prec == HDG_FP64 else HDG_MIXED) if asm_prec is None else asm_prec
         self.m = wl.gmres_m if m is None else m
         self.ctx = ctx or Context(wl.mesh, wl)
         c = self.ctx
