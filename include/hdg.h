@@ -235,7 +235,9 @@ int hdg_get_update_tile(const hdg_ctx *ctx, int n);
  *    [B | R_qu] (rows 0..n-1, columns n..n+f).
  * SK (all elements, element e at SK_off[e]) receives [S^K | g^K].
  * info[e] (device, all elements) = 0, or k+1 if the k-th pivot was zero or
- * not finite (the element's outputs are then undefined).
+ * not finite (the element's outputs are then undefined; the other elements'
+ * outputs are unaffected).  A NaN that is never a pivot candidate's maximum is
+ * not reported: it propagates to that element's outputs.
  */
 int hdg_condense(hdg_ctx *ctx, int prec, int refine_steps, int e0, int ne, double *E,
                  double *SK, int *info, void *work, size_t work_bytes, void *stream);

@@ -149,6 +149,27 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def descriptors(mesh, wl_or_phys):
+    """(hdg_mesh_desc, hdg_phys, arrays the descriptor points into) for a
+    mesh and a set of physical constants (argument marshalling only)."""
+    keep = dict(
+        vert=np.ascontiguousarray(mesh.vert_xyz, dtype=np.float64),
+        ev=np.ascontiguousarray(mesh.elem_vert, dtype=np.int32),
+        ef=np.ascontiguousarray(mesh.elem_face, dtype=np.int32),
+        fe=np.ascontiguousarray(mesh.face_elem, dtype=np.int32),
+        bc=np.ascontiguousarray(mesh.face_bc, dtype=np.int8),
+        p=np.ascontiguousarray(mesh.elem_p, dtype=np.int8))
+    geom = getattr(mesh, "elem_geom", None)
+    if geom is not None:
+        keep["geom"] = np.ascontiguousarray(geom, dtype=np.float64).reshape(mesh.n_elem, 27, 3)
+    desc = _MeshDesc(mesh.n_elem, mesh.n_face, mesh.n_vert, keep["vert"].ctypes.data, keep["ev"].ctypes.data,
+                     keep["ef"].ctypes.data, keep["fe"].ctypes.data, keep["bc"].ctypes.data, keep["p"].ctypes.data,
+                     keep["geom"].ctypes.data if geom is not None else None)
+    w = wl_or_phys
+    phys = _Phys(w.gamma, w.prandtl, w.reynolds, w.mach, w.tau, w.dt, w.alpha, int(w.visc_law))
+    return desc, phys, keep
+
+
 class Context:
     """An hdg_ctx for one mesh and one set of physical constants."""
 
@@ -158,22 +179,7 @@ class Context:
             raise HDGError("libhdg needs a GPU (torch.cuda.is_available() is False)")
         L = load_library()
         self.mesh = mesh
-        self._keep = dict(
-            vert=np.ascontiguousarray(mesh.vert_xyz, dtype=np.float64),
-            ev=np.ascontiguousarray(mesh.elem_vert, dtype=np.int32),
-            ef=np.ascontiguousarray(mesh.elem_face, dtype=np.int32),
-            fe=np.ascontiguousarray(mesh.face_elem, dtype=np.int32),
-            bc=np.ascontiguousarray(mesh.face_bc, dtype=np.int8),
-            p=np.ascontiguousarray(mesh.elem_p, dtype=np.int8))
-        geom = getattr(mesh, "elem_geom", None)
-        if geom is not None:
-            self._keep["geom"] = np.ascontiguousarray(geom, dtype=np.float64).reshape(mesh.n_elem, 27, 3)
-        k = self._keep
-        desc = _MeshDesc(mesh.n_elem, mesh.n_face, mesh.n_vert, k["vert"].ctypes.data, k["ev"].ctypes.data,
-                         k["ef"].ctypes.data, k["fe"].ctypes.data, k["bc"].ctypes.data, k["p"].ctypes.data,
-                         k["geom"].ctypes.data if geom is not None else None)
-        w = wl_or_phys
-        phys = _Phys(w.gamma, w.prandtl, w.reynolds, w.mach, w.tau, w.dt, w.alpha, int(w.visc_law))
+        desc, phys, self._keep = descriptors(mesh, wl_or_phys)
         torch.cuda.init()
         h = _vp()
         _check(L.hdg_create(ctypes.byref(desc), ctypes.byref(phys), ctypes.byref(h)), "hdg_create")

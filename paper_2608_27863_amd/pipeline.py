@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .hdg import HDG_FP64, HDG_MIXED, Context
+from .hdg import HDG_FP64, HDG_MIXED, Context, HDGError
 
 
 class NewtonStep:
@@ -179,6 +179,19 @@ class NewtonSolver:
         ctx.hdg_residual_norm(self.rwork, self.norms, stream)
         return tuple(float(v) for v in self.norms.cpu())
 
+    def pivot_failure(self):
+        """None, or which factorisation met a zero or non-finite pivot (the
+        device info arrays: k+1 for the k-th pivot) and in which element."""
+        import torch
+        st = self.st
+        for what, info in (("condensation", st.info), ("Schwarz set-up", st.asm_info)):
+            bad = torch.nonzero(info).flatten().cpu()
+            if bad.numel():
+                e = int(bad[0])
+                return (f"{what}: pivot {int(info[e])} of element {e} is zero or not finite"
+                        f" ({bad.numel()} element(s) affected)")
+        return None
+
     def solve(self, stream=None):
         """Returns the history [(||R_q||, ||R_u||, ||R_uh||, alpha, GMRES history), ...]."""
         import math
@@ -194,6 +207,9 @@ class NewtonSolver:
             st.condense(stream)
             st.assemble(stream)
             st.asm_setup(stream)
+            failed = self.pivot_failure()
+            if failed:
+                raise HDGError(f"Newton iteration {it}: {failed}")
             if self.rb_max and self.count:
                 ctx.hdg_rb_guess(self.count, self.W, self.Z, st.g, self.x0, self.rb_work, stream)
                 ctx.hdg_gmres_x0(st.asm_prec, st.S, st.Sinv, st.g, self.x0, st.m, st.dUhat, st.hist, st.gm_work,
