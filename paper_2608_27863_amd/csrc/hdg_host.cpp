@@ -304,7 +304,10 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
     ctx->elem_n.resize(ne);
     ctx->elem_f.resize(ne);
     ctx->face_off.assign(nf + 1, 0);
-    for (int F = 0; F < nf; ++F) ctx->face_off[F + 1] = ctx->face_off[F] + trace_size(ctx->face_p[F]);
+    for (int F = 0; F < nf; ++F) {
+        ctx->face_off[F + 1] = ctx->face_off[F] + trace_size(ctx->face_p[F]);
+        if (trace_size(ctx->face_p[F]) % 16 != 0) ctx->face_cols_aligned = false;
+    }
     for (int e = 0; e < ne; ++e) {
         int p = ctx->elem_p[e], Np = (p + 1) * (p + 1) * (p + 1), Nq = (p + 2) * (p + 2) * (p + 2);
         int n = 20 * Np, f = 0, nqf_tot = 0;
@@ -319,6 +322,8 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
         ctx->toff[7 * e + 6] = f;
         ctx->elem_n[e] = n;
         ctx->elem_f[e] = f;
+        if (f % 16 != 0) ctx->asm_cols_aligned64 = false;
+        if (f % 32 != 0) ctx->asm_cols_aligned32 = false;
         if (p != ctx->elem_p[0]) ctx->uniform_p = false;
         ctx->max_n = std::max(ctx->max_n, n);
         ctx->max_f = std::max(ctx->max_f, f);

@@ -103,6 +103,9 @@ struct hdg_ctx {
     int n_vclass = 0;  // vertex classes of the artificial-viscosity smoothing
     bool uniform_p = true;
     bool repeated_face = false;  // some element meets the same face twice
+    // whether every block column starts on a 128-byte line: the face blocks of
+    // S (b_F doubles) and the Schwarz inverses (f_e doubles, f_e floats)
+    bool face_cols_aligned = true, asm_cols_aligned64 = true, asm_cols_aligned32 = true;
     std::vector<int> elem_p, face_p, elem_face, face_elem, face_bc, toff, elem_n, elem_f;
     std::vector<int64_t> node_off, face_off, E_off, SK_off, asm_off, qp_off, vgeo_off, fgeo_off, asmsys_off,
         tloc_off, m32_off, x_off;

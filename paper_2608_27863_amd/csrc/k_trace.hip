@@ -15,7 +15,6 @@ namespace {
 
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-__device__ inline double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
 
 // ------------------------------------------------------------------ assembly
 __global__ void __launch_bounds__(256) k_assemble_blocks(DevMesh dm, const double *__restrict__ SK,
@@ -58,8 +57,16 @@ __global__ void __launch_bounds__(128) k_assemble_g(DevMesh dm, const double *__
 // -------------------------------------------------------------------- matvec
 constexpr int kMaxRowBlocks = 16;
 
+// One workgroup per face row; its 256 threads read each block's columns as one
+// contiguous run.  NT: streaming (nontemporal) loads, the choice when every
+// block column is whole 128-byte lines; otherwise columns share lines with
+// their neighbours, read by other waves, and plain loads let L2 serve the
+// second read (streaming loads fetched those lines twice: 1.19x the bytes of
+// S at p = 4, where a column is 1000 bytes).
+template <bool NT>
 __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__restrict__ S,
                                                 const double *__restrict__ x, double *__restrict__ y) {
+    auto ld = [](const double *p) { return NT ? __builtin_nontemporal_load(p) : *p; };
     const int F = blockIdx.x;
     const int bF = (int)(dm.face_off[F + 1] - dm.face_off[F]);
     const int k0 = dm.bsr_row_ptr[F], nk = dm.bsr_row_ptr[F + 1] - k0;
@@ -92,16 +99,16 @@ __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__rest
             const int bG = sxo[q + 1] - sxo[q];
             int j = w;
             for (; j + 3 * W < bG; j += 4 * W) {
-                const double a0 = ld_stream(blk + i + (int64_t)j * bF);
-                const double a1 = ld_stream(blk + i + (int64_t)(j + W) * bF);
-                const double a2 = ld_stream(blk + i + (int64_t)(j + 2 * W) * bF);
-                const double a3 = ld_stream(blk + i + (int64_t)(j + 3 * W) * bF);
+                const double a0 = ld(blk + i + (int64_t)j * bF);
+                const double a1 = ld(blk + i + (int64_t)(j + W) * bF);
+                const double a2 = ld(blk + i + (int64_t)(j + 2 * W) * bF);
+                const double a3 = ld(blk + i + (int64_t)(j + 3 * W) * bF);
                 acc += a0 * xs[j];
                 acc += a1 * xs[j + W];
                 acc += a2 * xs[j + 2 * W];
                 acc += a3 * xs[j + 3 * W];
             }
-            for (; j < bG; j += W) acc += ld_stream(blk + i + (int64_t)j * bF) * xs[j];
+            for (; j < bG; j += W) acc += ld(blk + i + (int64_t)j * bF) * xs[j];
         }
     }
     sred[threadIdx.x] = acc;
@@ -213,6 +220,54 @@ __global__ void __launch_bounds__(256) k_asm_local(DevMesh dm, const T *__restri
     }
     for (; j < f; ++j) acc += (double)M[(int64_t)j * f + i] * sy[j];
     zloc[dm.tloc_off[e] + i] = acc;
+}
+
+// The same product with one workgroup per element: each thread owns rows i,
+// i + 256, i + 512 (f <= 768), so every column of the inverse is read by one
+// workgroup, on one CU and one XCD's L2.  Used when the columns do not start
+// on 128-byte lines: a line shared by two columns is then read twice by the
+// same workgroup instead of by two workgroups on different XCDs (which fetch
+// it twice).  The sum runs over j in the same order as in k_asm_local, so the
+// two give identical results.
+constexpr int kAsmRowsPerThread = 3;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_asm_local_elem(DevMesh dm, const T *__restrict__ Sinv,
+                                                        const double *__restrict__ r, double *__restrict__ zloc) {
+    const int e = blockIdx.x;
+    const int *to = dm.toff + 7 * e;
+    const int f = to[6];
+    __shared__ double sy[kAsmRowsPerThread * 256];
+    for (int lf = 0; lf < 6; ++lf) {
+        const int F = dm.elem_face[6 * e + lf];
+        const int len = to[lf + 1] - to[lf];
+        for (int t = threadIdx.x; t < len; t += blockDim.x) sy[to[lf] + t] = r[dm.face_off[F] + t];
+    }
+    __syncthreads();
+    const T *M = Sinv + dm.asm_off[e];
+    int row[kAsmRowsPerThread];
+#pragma unroll
+    for (int q = 0; q < kAsmRowsPerThread; ++q) row[q] = min((int)threadIdx.x + 256 * q, f - 1);  // clamped reads
+    double acc[kAsmRowsPerThread] = {};
+    int j = 0;
+    for (; j + 3 < f; j += 4) {
+        T a[4][kAsmRowsPerThread];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < kAsmRowsPerThread; ++q) a[c][q] = M[(int64_t)(j + c) * f + row[q]];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < kAsmRowsPerThread; ++q) acc[q] += (double)a[c][q] * sy[j + c];
+    }
+    for (; j < f; ++j)
+#pragma unroll
+        for (int q = 0; q < kAsmRowsPerThread; ++q) acc[q] += (double)M[(int64_t)j * f + row[q]] * sy[j];
+    double *z = zloc + dm.tloc_off[e];
+#pragma unroll
+    for (int q = 0; q < kAsmRowsPerThread; ++q)
+        if ((int)threadIdx.x + 256 * q < f) z[threadIdx.x + 256 * q] = acc[q];
 }
 
 __global__ void __launch_bounds__(128) k_asm_gather(DevMesh dm, const double *__restrict__ zloc, double *__restrict__ z) {
@@ -624,7 +679,10 @@ int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, 
 }
 
 int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_matvec, dim3(ctx->n_face), dim3(256), 0, s, ctx->dm, S, x, y);
+    if (ctx->face_cols_aligned)
+        hipLaunchKernelGGL(k_matvec<true>, dim3(ctx->n_face), dim3(256), 0, s, ctx->dm, S, x, y);
+    else
+        hipLaunchKernelGGL(k_matvec<false>, dim3(ctx->n_face), dim3(256), 0, s, ctx->dm, S, x, y);
     return (int)hipGetLastError();
 }
 
@@ -668,10 +726,21 @@ int launch_asm_apply(const hdg_ctx *ctx, int prec, const void *Sinv, const doubl
     const DevMesh &dm = ctx->dm;
     double *zloc = (double *)work;
     const dim3 grid(ctx->n_elem, (ctx->max_f + 255) / 256);
-    if (prec == HDG_FP64)
-        hipLaunchKernelGGL(k_asm_local<double>, grid, dim3(256), 0, s, dm, (const double *)Sinv, r, zloc);
-    else
-        hipLaunchKernelGGL(k_asm_local<float>, grid, dim3(256), 0, s, dm, (const float *)Sinv, r, zloc);
+    const bool aligned = prec == HDG_FP64 ? ctx->asm_cols_aligned64 : ctx->asm_cols_aligned32;
+    const bool per_elem = !aligned && ctx->max_f <= kAsmRowsPerThread * 256;
+    if (prec == HDG_FP64) {
+        if (per_elem)
+            hipLaunchKernelGGL(k_asm_local_elem<double>, dim3(ctx->n_elem), dim3(256), 0, s, dm, (const double *)Sinv, r,
+                               zloc);
+        else
+            hipLaunchKernelGGL(k_asm_local<double>, grid, dim3(256), 0, s, dm, (const double *)Sinv, r, zloc);
+    } else {
+        if (per_elem)
+            hipLaunchKernelGGL(k_asm_local_elem<float>, dim3(ctx->n_elem), dim3(256), 0, s, dm, (const float *)Sinv, r,
+                               zloc);
+        else
+            hipLaunchKernelGGL(k_asm_local<float>, grid, dim3(256), 0, s, dm, (const float *)Sinv, r, zloc);
+    }
     hipLaunchKernelGGL(k_asm_gather, dim3(ctx->n_face), dim3(128), 0, s, dm, (const double *)zloc, z);
     return (int)hipGetLastError();
 }
