@@ -1593,7 +1593,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
     const int arow0 = (OP == 0) ? 0 : n;
     const double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
     const double *X = Xbase + (dm.x_off[e] - dm.x_off[e0]);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     __shared__ __attribute__((aligned(16))) double sA[2][kTM][C::SA];
     __shared__ __attribute__((aligned(16))) double sB[2][C::KC][C::SB];
@@ -1654,6 +1654,17 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
         while (ch < nchunks && !needed(ch)) ++ch;
         return ch;
     };
+    // the same test per 16-row block of this wave (uniform per wave): a block
+    // skips the products of a chunk whose columns are zero in all its rows
+    unsigned bmask[4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+        const int lo = r0 + wr + 16 * bi, hi = min(lo + 15, Mrows - 1);
+        bmask[bi] = 0;
+        if (OP != 0) bmask[bi] = 0xFFFFFu;
+        else if (lo < Mrows)
+            for (int fr = lo / Np; fr <= hi / Np; ++fr) bmask[bi] |= a_field_mask(fr);
+    }
     acc_t acc[4][4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
@@ -1670,6 +1681,13 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
     while (ch < nchunks) {
         const int nx = next_needed(ch + 1);
         if (nx < nchunks) load_chunk(nx * C::KC, ra, rb);
+        bool use[4];
+        {
+            const int k_lo = ch * C::KC, k_hi = min(k_lo + C::KC, K) - 1;
+            const unsigned span = ((2u << (k_hi / Np)) - 1u) & ~((1u << (k_lo / Np)) - 1u);
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) use[bi] = (bmask[bi] & span) != 0u;
+        }
 #pragma unroll
         for (int kk = 0; kk < C::KC; kk += 4) {
             double av[4], bv[4];
@@ -1679,8 +1697,9 @@ __global__ void __launch_bounds__(256, 2) k_gemm64(DevMesh dm, int e0, int ne, i
             for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][kk + (lane >> 4)][wc + 16 * bj + (lane & 15)];
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
+                if (use[bi])
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<double>::mfma(av[bi], bv[bj], acc[bi][bj]);
+                    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MF<double>::mfma(av[bi], bv[bj], acc[bi][bj]);
         }
         if (nx < nchunks) {
             store_chunk(buf ^ 1, nx * C::KC, ra, rb);
