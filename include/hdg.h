@@ -170,7 +170,10 @@ typedef enum {
     HDG_LAYOUT_BSR_VAL_OFF = 6, /* [nnzb+1] block offsets (doubles)                   */
     HDG_LAYOUT_ASM_OFF = 7,     /* [n_elem+1] Schwarz block offsets (entries)          */
     HDG_LAYOUT_ELEM_N = 8,      /* [n_elem] n_e                                       */
-    HDG_LAYOUT_ELEM_F = 9       /* [n_elem] f_e                                       */
+    HDG_LAYOUT_ELEM_F = 9,      /* [n_elem] f_e                                       */
+    HDG_LAYOUT_X_OFF = 10       /* [n_elem+1] retained-X offsets (doubles): element e's
+                                   X is row-major n_e x x_ld_e, x_ld_e = f_e + 1 rounded
+                                   up to a multiple of 8                               */
 } hdg_layout_kind;
 int hdg_layout(const hdg_ctx *ctx, int kind, int64_t *dst, int64_t capacity);
 /* Length of a layout array (so the caller can size dst). */
@@ -421,6 +424,23 @@ int hdg_residual_norm(hdg_ctx *ctx, void *work, size_t work_bytes, double *norms
  */
 int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E,
                          const double *dUhat, double *dQU, void *stream);
+
+/*
+ * Streamed condensation (the element systems of one chunk at a time; eq.
+ * local-elimination).  After hdg_condense(HDG_MIXED) of elements e0 .. e0+ne-1,
+ * X = A^{-1}[B | R_qu] is all that the recovery needs of their systems:
+ * hdg_store_x copies it (rows 0..n-1, columns n..n+f of each system in the
+ * chunk's E, laid out as for hdg_condense) into X (device, all elements,
+ * element e at x_off[e] of HDG_LAYOUT_X_OFF, padding columns zeroed), after
+ * which the chunk's E may be reused for the next chunk.
+ * hdg_recover_interior_x is hdg_recover_interior(HDG_MIXED) reading X from that
+ * store: d(Q,U)^K = -(x_r + X_B dUh^K) for elements e0 .. e0+ne-1.
+ * Both only enqueue; argument errors return HDG_ERR_INVALID_ARGUMENT before any
+ * launch.  E and X must not overlap.
+ */
+int hdg_store_x(hdg_ctx *ctx, int e0, int ne, const double *E, double *X, void *stream);
+int hdg_recover_interior_x(hdg_ctx *ctx, int e0, int ne, const double *X, const double *dUhat, double *dQU,
+                           void *stream);
 
 /*
  * The whole hot path of one Newton iteration (figure "Computational workflow":

@@ -543,6 +543,7 @@ int64_t hdg_layout_length(const hdg_ctx *ctx, int kind) {
     if (!ctx) return -1;
     switch (kind) {
         case HDG_LAYOUT_NODE_OFF: case HDG_LAYOUT_E_OFF: case HDG_LAYOUT_SK_OFF: case HDG_LAYOUT_ASM_OFF:
+        case HDG_LAYOUT_X_OFF:
             return ctx->n_elem + 1;
         case HDG_LAYOUT_FACE_OFF: case HDG_LAYOUT_BSR_ROW_PTR: return ctx->n_face + 1;
         case HDG_LAYOUT_BSR_COL: return (int64_t)ctx->bsr_col.size();
@@ -563,6 +564,7 @@ int hdg_layout(const hdg_ctx *ctx, int kind, int64_t *dst, int64_t capacity) {
         case HDG_LAYOUT_E_OFF: v = &ctx->E_off; break;
         case HDG_LAYOUT_SK_OFF: v = &ctx->SK_off; break;
         case HDG_LAYOUT_ASM_OFF: v = &ctx->asm_off; break;
+        case HDG_LAYOUT_X_OFF: v = &ctx->x_off; break;
         case HDG_LAYOUT_BSR_ROW_PTR: v = &ctx->bsr_row_ptr64; break;
         case HDG_LAYOUT_BSR_COL: v = &ctx->bsr_col64; break;
         case HDG_LAYOUT_BSR_VAL_OFF: v = &ctx->bsr_val_off; break;
@@ -767,6 +769,17 @@ int hdg_recover_interior(hdg_ctx *ctx, int prec, int e0, int ne, const double *E
         return HDG_ERR_INVALID_ARGUMENT;
     if (prec == HDG_MIXED_FAST) prec = HDG_FP64;  // E holds U and L^{-1} P [B | R_qu] in either case
     return dev_status(hdg::launch_recover(ctx, prec, e0, ne, E, dUhat, dQU, (hipStream_t)stream));
+}
+
+int hdg_store_x(hdg_ctx *ctx, int e0, int ne, const double *E, double *X, void *stream) {
+    if (!chunk_ok(ctx, e0, ne) || !E || !X) return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_store_x(ctx, e0, ne, E, X, (hipStream_t)stream));
+}
+
+int hdg_recover_interior_x(hdg_ctx *ctx, int e0, int ne, const double *X, const double *dUhat, double *dQU,
+                           void *stream) {
+    if (!chunk_ok(ctx, e0, ne) || !X || !dUhat || !dQU) return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_recover_x(ctx, e0, ne, X, dUhat, dQU, (hipStream_t)stream));
 }
 
 // ------------------------------------------------------ the whole step

@@ -171,4 +171,7 @@ int launch_av_field(const hdg_ctx *ctx, const AvParams &ap, const double *U, con
                     double *nu, void *work, hipStream_t s);
 int launch_recover(const hdg_ctx *ctx, int prec, int e0, int ne, const double *E,
                    const double *dUhat, double *dQU, hipStream_t s);
+int launch_store_x(const hdg_ctx *ctx, int e0, int ne, const double *E, double *X, hipStream_t s);
+int launch_recover_x(const hdg_ctx *ctx, int e0, int ne, const double *X, const double *dUhat, double *dQU,
+                     hipStream_t s);
 }  // namespace hdg

@@ -584,14 +584,19 @@ __global__ void __launch_bounds__(256) k_admissible(DevMesh dm, double alpha, do
 // with the block's solution.
 constexpr int kRB = 64, kRT = 1024, kRW = kRT / 64, kRQ = 4;  // kRQ rows in flight per wave
 
+// Y = [Y_B | y_r] is read from the chunk's element systems (columns n.., row
+// stride e_ld) or, with Xbase, from the retained X (columns 0.., stride x_ld).
 __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub, const double *__restrict__ Ebase,
-                                                 const double *__restrict__ dUhat, double *__restrict__ dQU) {
+                                                 const double *__restrict__ Xbase, const double *__restrict__ dUhat,
+                                                 double *__restrict__ dQU) {
     const int e = e0 + blockIdx.x;
     const int p = dm.elem_p[e], Np = (p + 1) * (p + 1) * (p + 1), n = 20 * Np;
     const int *to = dm.toff + 7 * e;
     const int f = to[6];
     const int64_t ld = e_ld(n, f);
-    const double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    const double *E = Xbase ? nullptr : Ebase + (dm.E_off[e] - dm.E_off[e0]);
+    const double *Y = Xbase ? Xbase + dm.x_off[e] : E + n;
+    const int64_t ldy = Xbase ? x_ld(f) : ld;
     __shared__ double sd[750];
     __shared__ double sy[2500];
     __shared__ double sU[kRB][kRB + 1];
@@ -615,12 +620,12 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
             const double dj = sd[j];
 #pragma unroll
             for (int q = 0; q < kRQ; ++q)
-                if (i + q < n) acc[q] += E[(int64_t)(i + q) * ld + n + j] * dj;
+                if (i + q < n) acc[q] += Y[(int64_t)(i + q) * ldy + j] * dj;
         }
 #pragma unroll
         for (int q = 0; q < kRQ; ++q) {
             const double v = wave_sum(acc[q]);
-            if (lane == 0 && i + q < n) sy[i + q] = v + E[(int64_t)(i + q) * ld + n + f];
+            if (lane == 0 && i + q < n) sy[i + q] = v + Y[(int64_t)(i + q) * ldy + f];
         }
     }
     __syncthreads();
@@ -661,6 +666,26 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
     }
     double *out = dQU + 20 * dm.node_off[e];
     for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = -sy[i];
+}
+
+// X of one element (rows 0..n-1, columns n..n+f of its condensed system) to
+// the retained store, kStoreXRows rows per workgroup, padding columns zeroed.
+constexpr int kStoreXRows = 16;
+__global__ void __launch_bounds__(256) k_store_x(DevMesh dm, int e0, const double *__restrict__ Ebase,
+                                                 double *__restrict__ X) {
+    const int e = e0 + blockIdx.y;
+    const int p = dm.elem_p[e], n = 20 * (p + 1) * (p + 1) * (p + 1);
+    const int f = dm.toff[7 * e + 6];
+    const int r0 = blockIdx.x * kStoreXRows;
+    if (r0 >= n) return;
+    const int64_t ld = e_ld(n, f), xl = x_ld(f);
+    const double *E = Ebase + (dm.E_off[e] - dm.E_off[e0]) + n;
+    double *Xe = X + dm.x_off[e];
+    const int rows = min(kStoreXRows, n - r0);
+    for (int t = threadIdx.x; t < rows * xl; t += blockDim.x) {
+        const int r = r0 + t / (int)xl, c = t % (int)xl;
+        Xe[(int64_t)r * xl + c] = c <= f ? E[(int64_t)r * ld + c] : 0.0;
+    }
 }
 
 inline int grid_for(int64_t n, int threads = 256, int cap = 2048) {
@@ -993,7 +1018,20 @@ int launch_admissible(const hdg_ctx *ctx, double alpha, const double *U, const d
 
 int launch_recover(const hdg_ctx *ctx, int prec, int e0, int ne, const double *E, const double *dUhat, double *dQU,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_recover, dim3(ne), dim3(kRT), 0, s, ctx->dm, e0, prec == HDG_FP64 ? 1 : 0, E, dUhat, dQU);
+    hipLaunchKernelGGL(k_recover, dim3(ne), dim3(kRT), 0, s, ctx->dm, e0, prec == HDG_FP64 ? 1 : 0, E,
+                       (const double *)nullptr, dUhat, dQU);
+    return (int)hipGetLastError();
+}
+
+int launch_recover_x(const hdg_ctx *ctx, int e0, int ne, const double *X, const double *dUhat, double *dQU,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_recover, dim3(ne), dim3(kRT), 0, s, ctx->dm, e0, 0, (const double *)nullptr, X, dUhat, dQU);
+    return (int)hipGetLastError();
+}
+
+int launch_store_x(const hdg_ctx *ctx, int e0, int ne, const double *E, double *X, hipStream_t s) {
+    hipLaunchKernelGGL(k_store_x, dim3((ctx->max_n + kStoreXRows - 1) / kStoreXRows, ne), dim3(256), 0, s, ctx->dm, e0,
+                       E, X);
     return (int)hipGetLastError();
 }
 

@@ -21,11 +21,12 @@ HDG_MIXED = 1
 HDG_MIXED_FAST = 2  # all-FP32 condensation, reported beside HDG_MIXED
 
 LAYOUT = {"node_off": 0, "face_off": 1, "E_off": 2, "SK_off": 3, "bsr_row_ptr": 4, "bsr_col": 5,
-          "bsr_val_off": 6, "asm_off": 7, "elem_n": 8, "elem_f": 9}
+          "bsr_val_off": 6, "asm_off": 7, "elem_n": 8, "elem_f": 9, "x_off": 10}
 
 EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_layout_length",
            "hdg_workspace_size", "hdg_local_residual_jacobian", "hdg_condense", "hdg_assemble_trace",
            "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior",
+           "hdg_store_x", "hdg_recover_interior_x",
            "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy",
            "hdg_asm_block_apply_noalloc", "hdg_gmres_x0", "hdg_rb_guess", "hdg_rb_insert", "hdg_state_update",
            "hdg_state_admissible", "hdg_lincomb", "hdg_residual_gather", "hdg_residual_norm", "hdg_av_field",
@@ -96,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     L.hdg_asm_block_apply.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.hdg_gmres.argtypes = [_vp, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.hdg_recover_interior.argtypes = [_vp, _i, _i, _i, _vp, _vp, _vp, _vp]
+    L.hdg_store_x.argtypes = [_vp, _i, _i, _vp, _vp, _vp]
+    L.hdg_recover_interior_x.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _vp]
     L.hdg_newton_step.argtypes = [_vp, ctypes.POINTER(_NewtonArgs), _vp]
     L.hdg_graph_capture_newton.argtypes = [_vp, ctypes.POINTER(_NewtonArgs), ctypes.POINTER(_vp), _vp]
     L.hdg_graph_launch.argtypes = [_vp, _vp]
@@ -292,6 +295,20 @@ class Context:
                                          _ptr(dUhat, torch.float64, self.N_uh, "dUhat"),
                                          _ptr(dQU, torch.float64, 20 * nn, "dQU"), _stream(stream))
         _check(rc, "hdg_recover_interior")
+
+    def hdg_store_x(self, e0, ne, E, X, stream=None):
+        import torch
+        rc = self.L.hdg_store_x(self.h, e0, ne, _ptr(E, torch.float64, self.e_size(e0, ne), "E"),
+                                _ptr(X, torch.float64, int(self.layout["x_off"][-1]), "X"), _stream(stream))
+        _check(rc, "hdg_store_x")
+
+    def hdg_recover_interior_x(self, e0, ne, X, dUhat, dQU, stream=None):
+        import torch
+        nn = int(self.layout["node_off"][-1])
+        rc = self.L.hdg_recover_interior_x(self.h, e0, ne, _ptr(X, torch.float64, int(self.layout["x_off"][-1]), "X"),
+                                           _ptr(dUhat, torch.float64, self.N_uh, "dUhat"),
+                                           _ptr(dQU, torch.float64, 20 * nn, "dQU"), _stream(stream))
+        _check(rc, "hdg_recover_interior_x")
 
     def hdg_asm_block_apply_noalloc(self, prec, Sinv, r, z, stream=None):
         import torch

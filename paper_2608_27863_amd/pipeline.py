@@ -16,10 +16,16 @@ from .hdg import HDG_FP64, HDG_MIXED, Context, HDGError
 
 class NewtonStep:
     def __init__(self, wl, prec=HDG_FP64, refine_steps=1, asm_prec=None, chunk=None, m=None,
-                 ctx=None, device="cuda", share=None):
+                 ctx=None, device="cuda", share=None, stream_E=False):
         """share: another NewtonStep on the same context whose device buffers are
         reused where shape and type agree (the two steps then overwrite each
-        other's results; useful when the element systems are large)."""
+        other's results; useful when the element systems are large).
+        stream_E (HDG_MIXED only): one chunk's element systems at a time.  E
+        holds the largest chunk; each chunk is assembled, condensed and its
+        X = A^{-1}[B | R_qu] copied to a resident store (hdg_store_x) before the
+        next chunk reuses E; the recovery reads that store
+        (hdg_recover_interior_x).  At p = 4 that is 15 MB per element instead
+        of the system's 84.5 MB."""
         import torch
         self.wl = wl
         self.prec = prec
@@ -56,7 +62,15 @@ class NewtonStep:
 
         self.Q, self.U, self.Un = inp("Q", wl.Q), inp("U", wl.U), inp("Un", wl.Un)
         self.Uhat, self.nu, self.Ub = inp("Uhat", wl.Uhat), inp("nu", wl.nu), inp("Ub", wl.Ub)
-        self.E = buf("E", int(c.layout["E_off"][-1]))
+        self.stream_E = bool(stream_E)
+        if self.stream_E and prec != HDG_MIXED:
+            raise ValueError("stream_E needs HDG_MIXED (the recovery then reads only X)")
+        if self.stream_E:
+            eo = c.layout["E_off"]
+            self.E = buf("E", max(int(eo[e0 + n] - eo[e0]) for e0, n in self.chunks))
+            self.X = buf("X", int(c.layout["x_off"][-1]))
+        else:
+            self.E = buf("E", int(c.layout["E_off"][-1]))
         qp = max(c.workspace_size(0, HDG_FP64, e0, n) for e0, n in self.chunks)
         self.qp_work = buf("qp_work", qp, torch.uint8)
         cw = max(c.workspace_size(1, prec, e0, n) for e0, n in self.chunks)
@@ -76,19 +90,32 @@ class NewtonStep:
 
     def E_chunk(self, e0, n):
         o = self.ctx.layout["E_off"]
+        if self.stream_E:
+            return self.E[:int(o[e0 + n] - o[e0])]
         return self.E[int(o[e0]):int(o[e0 + n])]
+
+    def _rj(self, e0, n, stream=None):
+        self.ctx.hdg_local_residual_jacobian(e0, n, self.Q, self.U, self.Un, self.Uhat, self.nu,
+                                             self.Ub if self.wl.mesh.face_bc.any() else None,
+                                             self.E_chunk(e0, n), self.qp_work, stream)
 
     # the steps of the hot path
     def residual_jacobian(self, stream=None):
+        """Element systems of every chunk (resident E).  With stream_E the
+        systems are formed chunk by chunk inside condense()."""
+        if self.stream_E:
+            return
         for e0, n in self.chunks:
-            self.ctx.hdg_local_residual_jacobian(e0, n, self.Q, self.U, self.Un, self.Uhat, self.nu,
-                                                 self.Ub if self.wl.mesh.face_bc.any() else None,
-                                                 self.E_chunk(e0, n), self.qp_work, stream)
+            self._rj(e0, n, stream)
 
     def condense(self, stream=None):
         for e0, n in self.chunks:
+            if self.stream_E:
+                self._rj(e0, n, stream)
             self.ctx.hdg_condense(self.prec, self.refine, e0, n, self.E_chunk(e0, n), self.SK, self.info,
                                   self.cond_work, stream)
+            if self.stream_E:
+                self.ctx.hdg_store_x(e0, n, self.E_chunk(e0, n), self.X, stream)
 
     def assemble(self, stream=None):
         self.ctx.hdg_assemble_trace(self.SK, self.S, self.g, stream)
@@ -101,11 +128,16 @@ class NewtonStep:
                            self.gm_work, stream)
 
     def recover(self, stream=None):
+        if self.stream_E:
+            self.ctx.hdg_recover_interior_x(0, self.ctx.n_elem, self.X, self.dUhat, self.dQU, stream)
+            return
         for e0, n in self.chunks:
             self.ctx.hdg_recover_interior(self.prec, e0, n, self.E_chunk(e0, n), self.dUhat, self.dQU, stream)
 
     def run(self, stream=None):
         """The whole hot path for one Newton step, as one call (hdg_newton_step)."""
+        if self.stream_E:
+            raise ValueError("the one-call step keeps every element system resident; use run_calls")
         if getattr(self, "_args", None) is None:
             self._args = self.ctx.newton_args(self)
         self.ctx.hdg_newton_step(self._args, stream)
@@ -126,6 +158,8 @@ class NewtonStep:
         contents of the input buffers; nothing is allocated or synchronised
         inside."""
         import torch
+        if self.stream_E:
+            raise ValueError("the captured step keeps every element system resident")
         if getattr(self, "_args", None) is None:
             self._args = self.ctx.newton_args(self)
         s = stream if stream is not None else torch.cuda.Stream()
