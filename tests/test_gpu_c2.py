@@ -106,7 +106,7 @@ def test_mixed_stores_refined_interior_solution(c0m):
     ne = c0m["wl"].mesh.n_elem
     worst = max(rel_err(_x_view(st.ctx, gpu["E"], e), ora[e]["X"]) for e in range(ne))
     ref = max(rel_err(_lapack_mixed_x(ora[e]["E"], int(st.ctx.layout["elem_n"][e])), ora[e]["X"])
-              for e in range(0, ne, 7))
+              for e in range(ne))  # the same elements on both sides
     print(f"  X = A^-1 [B | R_qu]: {worst:.3e}  (same recipe through LAPACK: {ref:.3e})")
     assert worst <= 10.0 * ref
 
@@ -165,11 +165,10 @@ def test_mixed_recovery(c0m):
         got = gpu["dQU"][20 * int(no[e]):20 * int(no[e + 1])]
         es, _ = recovery_error(wl, e, ora[e]["X"], gpu["dUhat"], got)
         worst = max(worst, es)
-        if e % 7 == 0:
-            Xl = _lapack_mixed_x(ora[e]["E"], sz.n(e))
-            d = O.gather_trace(wl, sz, e, gpu["dUhat"])
-            er, _ = recovery_error(wl, e, ora[e]["X"], gpu["dUhat"], -(Xl[:, -1] + Xl[:, :-1] @ d))
-            ref = max(ref, er)
+        Xl = _lapack_mixed_x(ora[e]["E"], sz.n(e))
+        d = O.gather_trace(wl, sz, e, gpu["dUhat"])
+        er, _ = recovery_error(wl, e, ora[e]["X"], gpu["dUhat"], -(Xl[:, -1] + Xl[:, :-1] @ d))
+        ref = max(ref, er)
     print(f"  d(Q,U): {worst:.3e} of the magnitude of its summands (LAPACK recipe: {ref:.3e})")
     assert worst <= max(10.0 * ref, 1e-12)
 
