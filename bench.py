@@ -184,8 +184,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default 128-row update tiles")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU's partition only (--gpus {args.gpus} requested); "
-              "sharding across GPUs is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: measures one GPU's partition only (--gpus {args.gpus} requested); "
+              "element-partition sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1:
         print("bench.py: --steps must be at least 1", file=sys.stderr)

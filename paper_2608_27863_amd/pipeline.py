@@ -27,6 +27,8 @@ class NewtonStep:
         (hdg_recover_interior_x).  At p = 4 that is 15 MB per element instead
         of the system's 84.5 MB."""
         import torch
+        if stream_E and prec != HDG_MIXED:
+            raise ValueError("stream_E needs HDG_MIXED (the recovery then reads only X)")
         self.wl = wl
         self.prec = prec
         self.refine = refine_steps
@@ -63,8 +65,6 @@ class NewtonStep:
         self.Q, self.U, self.Un = inp("Q", wl.Q), inp("U", wl.U), inp("Un", wl.Un)
         self.Uhat, self.nu, self.Ub = inp("Uhat", wl.Uhat), inp("nu", wl.nu), inp("Ub", wl.Ub)
         self.stream_E = bool(stream_E)
-        if self.stream_E and prec != HDG_MIXED:
-            raise ValueError("stream_E needs HDG_MIXED (the recovery then reads only X)")
         if self.stream_E:
             eo = c.layout["E_off"]
             self.E = buf("E", max(int(eo[e0 + n] - eo[e0]) for e0, n in self.chunks))
