@@ -22,6 +22,8 @@
 namespace hdg {
 namespace {
 
+typedef double v2d __attribute__((ext_vector_type(2)));
+
 // ------------------------------------------------------------------ physics
 // Intermediates at one point for state w and conservative gradient q.
 struct PState {
@@ -553,7 +555,12 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
     };
 
     if (qrow) {
-        // mass block and K_j (identical for every component c); zeros elsewhere
+        // zeros over all n interior columns first (16-byte stores; n = 20 N_p is even and
+        // the rows start on 64 bytes), then the mass block and K_j (identical for every
+        // component c) over their columns; volume_block begins with a barrier
+        const v2d zero2 = {0.0, 0.0};
+        for (int t = tid; t < Np * (n / 2); t += blockDim.x)
+            *(v2d *)(Er + (int64_t)(t / (n / 2)) * ld + 2 * (t % (n / 2))) = zero2;
         for (int kind = 0; kind < 2; ++kind) {
             __syncthreads();
             for (int t = tid; t < 4 * Nq; t += blockDim.x) {
@@ -565,10 +572,6 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
             }
             volume_block(kind == 0 ? r : 15 + c, false);
         }
-        const int z0 = r * Np, z1 = (15 + c) * Np;
-        for (int i = 0; i < Np; ++i)
-            for (int col = tid; col < n; col += blockDim.x)
-                if ((col < z0 || col >= z0 + Np) && (col < z1 || col >= z1 + Np)) Er[(int64_t)i * ld + col] = 0.0;
     } else {
         for (int sblk = ug * 20 / kUG; sblk < (ug + 1) * 20 / kUG; ++sblk) {
             const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
@@ -630,27 +633,42 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
             sF[t] = v;
         }
         __syncthreads();
-        const int ncol = 5 * Nfp;
-        for (int t = tid; t < Np * ncol; t += blockDim.x) {
-            const int i = t / ncol, col = t % ncol;
-            const int cp = col / Nfp, b = col % Nfp;
-            const int i1 = i % p1, i2 = (i / p1) % p1, i3 = i / (p1 * p1);
-            int a0, a1;
-            const double v = face_idx(i1, i2, i3, lf, a0, a1) ? sF[(cp * p1 * p1 + a0 * p1 + a1) * Nfp + b] : 0.0;
-            Er[(int64_t)i * ld + n + toff[lf] + col] = v;
+        // a thread keeps one column (ncol = 5 N_fp <= 125) and walks rows; a row
+        // off the face is zero, a row on it reads its face-local index a0 p1 + a1
+        const int ncol = 5 * Nfp, groups = blockDim.x / ncol;
+        if (tid < groups * ncol) {
+            const int col = tid % ncol, cp = col / Nfp, b = col % Nfp;
+            const double *fc = sF + cp * p1 * p1 * Nfp + b;
+            double *dst = Er + n + toff[lf] + col;
+            for (int i = tid / ncol; i < Np; i += groups)
+                dst[(int64_t)i * ld] = ((sNm[i] >> lf) & 1u) ? fc[sNa[lf][i] * Nfp] : 0.0;
         }
     }
-    // ---- residual column and padding
-    for (int i = tid; i < Np; i += blockDim.x) {
-        double v = 0.0;
+    // ---- residual column and padding: the residual's point coefficients in LDS,
+    // the sum over the Gauss points split over two halves of the threads
+    __syncthreads();
+    {
         const double *rc = qpe + (int64_t)kVJac * Nq + (int64_t)(4 * r) * Nq;
+        for (int t = tid; t < 4 * Nq; t += blockDim.x) sC[t / Nq][t % Nq] = rc[t];
+    }
+    __syncthreads();
+    static_assert(2 * Np <= 256, "two threads per row");
+    if (tid < 2 * Np) {
+        const int i = tid % Np, h = tid / Np;
         const int i1 = i % p1, i2 = (i / p1) % p1, i3 = i / (p1 * p1);
-        for (int g = 0; g < Nq; ++g) {
+        double v = 0.0;
+        for (int g = h * (Nq / 2); g < (h + 1) * (Nq / 2) + h * (Nq % 2); ++g) {
             const int g1 = g % nq, g2 = (g / nq) % nq, g3 = g / (nq * nq);
             const double l0 = sL[i1][g1], l1 = sL[i2][g2], l2 = sL[i3][g3];
-            v += rc[g] * l0 * l1 * l2 + rc[Nq + g] * sD[i1][g1] * l1 * l2 + rc[2 * Nq + g] * l0 * sD[i2][g2] * l2 +
-                 rc[3 * Nq + g] * l0 * l1 * sD[i3][g3];
+            v += sC[0][g] * l0 * l1 * l2 + sC[1][g] * sD[i1][g1] * l1 * l2 + sC[2][g] * l0 * sD[i2][g2] * l2 +
+                 sC[3][g] * l0 * l1 * sD[i3][g3];
         }
+        sG[tid] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < Np; i += blockDim.x) {
+        double v = sG[i] + sG[Np + i];
+        const int i1 = i % p1, i2 = (i / p1) % p1, i3 = i / (p1 * p1);
         for (int lf = 0; lf < 6; ++lf) {
             int a0, a1;
             if (!face_idx(i1, i2, i3, lf, a0, a1)) continue;
