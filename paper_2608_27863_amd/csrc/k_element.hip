@@ -690,14 +690,17 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
 // workgroup per (face, element): the numerical flux on an interior face, the
 // boundary residual on a boundary face.  Only the columns of the face's own
 // nodes (C), of the face's trace block (D) and the residual column are
-// nonzero.  A table maps every column once to its basis function (or
-// to zero); each pass forms, for kTR rows (c, a), the weights
-// w(slot, s) = coefficient(c, slot)(s) mu_a(s) at the face's Gauss points, so
-// that a nonzero entry is one dot product over the Gauss points with phi_k(s)
-// (C) or mu_b(s) (D), and a row is written in one coalesced sweep.
-constexpr int kTR = 4;                              // trace rows per pass
+// nonzero.  Rows go component by component (c = row / N_fp), kTR rows per
+// pass.  In a pass each thread takes one (row, slot) pair (slots 0..19: C by
+// column field, 20..24: D by trace component, 25: the residual column), forms
+// its weights w(s) = coefficient(c, slot)(s) mu_a(s) at the face's Gauss
+// points in registers and all of the pair's entries as dot products over the
+// Gauss points with phi_k(s) (C) or mu_b(s) (D), into a compact LDS row; a
+// column map then writes every row in one coalesced sweep, zeros included.
+constexpr int kTR = 8;                              // trace rows per pass
 constexpr int kNqfMax = kNQ * kNQ, kNfpMax = kP1 * kP1;
 constexpr int kLdMax = (20 * kP1 * kP1 * kP1 + 30 * kNfpMax + 1 + 7) / 8 * 8;
+constexpr int kTOut = 20 * kNfpMax + 5 * kNfpMax + 1;  // nonzero entries of a trace row, at most
 
 __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P, int e0, const double *__restrict__ qp,
                                                              double *__restrict__ Ebase) {
@@ -713,93 +716,84 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
     __shared__ int sPf[6], sNqf[6];
     __shared__ int64_t sFbase[6];
     __shared__ double sPhi[kNfpMax][kNqfMax], sMu[kNfpMax][kNqfMax];
-    __shared__ double sW[kTR][26][kNqfMax];
     __shared__ double sK[26][kNqfMax];  // coefficients of the current component c
-    __shared__ int sMap[kLdMax];
+    __shared__ double sOut[kTR][kTOut];  // the nonzero entries of the pass's rows
+    __shared__ int sMap[kLdMax];         // column -> index into a row of sOut, or -1
     load_face_tables(dm, e, p, Nq, sLf, sMf, sPf, sNqf, sFbase);
     __syncthreads();
     const int pf1 = sPf[lf] + 1, nqf1 = pf1 + 1, Nfp = pf1 * pf1, Nqf = sNqf[lf];
     const int F = dm.elem_face[6 * e + lf], bc = dm.face_bc[F];
     const double *fb = qpe + sFbase[lf];
     double *Et = E + (int64_t)(n + toff[lf]) * ld;
-    const int nrow = 5 * Nfp;
+    const int nC = 20 * p1 * p1;  // C entries of a row: column field x, face node y at x p1^2 + y
     // element basis phi_k and trace basis mu_b at the face's Gauss points
     for (int t = tid; t < kNfpMax * Nqf; t += blockDim.x) {
         const int k = t / Nqf, sq = t % Nqf, s0 = sq % nqf1, s1 = sq / nqf1;
         sPhi[k][sq] = (k < p1 * p1) ? sLf[lf][(k % p1) * nqf1 + s0] * sLf[lf][(k / p1) * nqf1 + s1] : 0.0;
         sMu[k][sq] = (k < Nfp) ? sMf[lf][(k % pf1) * nqf1 + s0] * sMf[lf][(k / pf1) * nqf1 + s1] : 0.0;
     }
-    // column map: -1 zero; (0, slot, ka0 + p1 ka1) C; (1, cp, b) D; (2) residual
     for (int col = tid; col < ld; col += blockDim.x) {
-        int code = -1;
+        int idx = -1;
         if (col < n) {
             const int sblk = col / Np, k = col % Np;
             int ka0, ka1;
             if (on_face(k, p1, lf, ka0, ka1)) {
                 const int slot = (sblk < 15) ? 5 + sblk : sblk - 15;
-                code = (slot << 8) | (ka0 + p1 * ka1);
+                idx = slot * p1 * p1 + ka0 + p1 * ka1;
             }
         } else if (col < n + f) {
             const int cc = col - n;
-            if (cc >= toff[lf] && cc < toff[lf + 1]) {
-                const int cp = (cc - toff[lf]) / Nfp, b = (cc - toff[lf]) % Nfp;
-                code = (1 << 16) | (cp << 8) | b;
-            }
+            if (cc >= toff[lf] && cc < toff[lf + 1]) idx = nC + (cc - toff[lf]);
         } else if (col == n + f) {
-            code = 2 << 16;
+            idx = nC + 5 * Nfp;
         }
-        sMap[col] = code;
+        sMap[col] = idx;
     }
-    // rows go component by component (c = row / Nfp); a component's
-    // coefficients at the Gauss points are staged in LDS once
-    int c_loaded = -1;
-    for (int r0 = 0; r0 < nrow; r0 += kTR) {
+    const int rr_t = tid / 26, slot_t = tid % 26;  // this thread's (row of the pass, slot)
+    for (int c = 0; c < 5; ++c) {
         __syncthreads();
-        const int c_lo = r0 / Nfp, c_hi = min(r0 + kTR - 1, nrow - 1) / Nfp;
-        // weights of rows r0 .. r0+kTR-1: slots 0..24 (C by column field, D by
-        // trace component), 25 the residual column
-        for (int cc = c_lo; cc <= c_hi; ++cc) {
-            if (cc != c_loaded) {
-                for (int t = tid; t < 26 * Nqf; t += blockDim.x) {
-                    const int slot = t / Nqf, sq = t % Nqf;
-                    double k;
-                    if (slot == 25) k = fb[(int64_t)((bc ? 130 : 125) + cc) * Nqf + sq];
-                    else k = fb[(int64_t)((bc ? 140 : 0) + 25 * cc + slot) * Nqf + sq];
-                    sK[slot][sq] = k;
-                }
-                c_loaded = cc;
-                __syncthreads();
-            }
-            for (int t = tid; t < kTR * 26 * Nqf; t += blockDim.x) {
-                const int rr = t / (26 * Nqf), rem = t % (26 * Nqf), slot = rem / Nqf, sq = rem % Nqf;
-                const int row = r0 + rr;
-                if (row < nrow && row / Nfp == cc) sW[rr][slot][sq] = sK[slot][sq] * sMu[row % Nfp][sq];
-                else if (row >= nrow) sW[rr][slot][sq] = 0.0;
-            }
-            __syncthreads();
+        for (int t = tid; t < 26 * Nqf; t += blockDim.x) {
+            const int slot = t / Nqf, sq = t % Nqf;
+            sK[slot][sq] = (slot == 25) ? fb[(int64_t)((bc ? 130 : 125) + c) * Nqf + sq]
+                                        : fb[(int64_t)((bc ? 140 : 0) + 25 * c + slot) * Nqf + sq];
         }
-#pragma unroll 1
-        for (int rr = 0; rr < kTR; ++rr) {
-            const int row = r0 + rr;
-            if (row >= nrow) break;
-            double *dst = Et + (int64_t)row * ld;
-            for (int col = tid; col < ld; col += blockDim.x) {
-                const int code = sMap[col];
-                double v = 0.0;
-                if (code >= 0) {
-                    // unrolled so that the LDS loads of a dot product are in flight together
-                    const int kind = code >> 16, x = (code >> 8) & 255, y = code & 255;
-                    const double *wrow = sW[rr][kind == 0 ? x : (kind == 1 ? 20 + x : 25)];
-                    const double *brow = kind == 0 ? sPhi[y] : sMu[y];
-                    if (kind == 2) {
-#pragma unroll 8
-                        for (int sq = 0; sq < Nqf; ++sq) v += wrow[sq];
-                    } else {
-#pragma unroll 8
-                        for (int sq = 0; sq < Nqf; ++sq) v += wrow[sq] * brow[sq];
+        for (int a0 = 0; a0 < Nfp; a0 += kTR) {
+            const int nr = min(kTR, Nfp - a0);
+            __syncthreads();  // sK ready; the previous pass's sweep is done with sOut
+            if (rr_t < nr) {
+                const int a = a0 + rr_t;  // trace row c Nfp + a tests mu_a
+                double w[kNqfMax];
+#pragma unroll
+                for (int sq = 0; sq < kNqfMax; ++sq) w[sq] = sq < Nqf ? sK[slot_t][sq] * sMu[a][sq] : 0.0;
+                double *out = sOut[rr_t];
+                if (slot_t == 25) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int sq = 0; sq < kNqfMax; ++sq)
+                        if (sq < Nqf) v += w[sq];
+                    out[nC + 5 * Nfp] = v;
+                } else {
+                    const bool isC = slot_t < 20;
+                    const int ny = isC ? p1 * p1 : Nfp;
+                    double *o = isC ? out + slot_t * p1 * p1 : out + nC + (slot_t - 20) * Nfp;
+                    for (int y = 0; y < ny; ++y) {
+                        const double *brow = isC ? sPhi[y] : sMu[y];
+                        double v = 0.0;
+#pragma unroll
+                        for (int sq = 0; sq < kNqfMax; ++sq)
+                            if (sq < Nqf) v += w[sq] * brow[sq];
+                        o[y] = v;
                     }
                 }
-                dst[col] = v;
+            }
+            __syncthreads();
+            for (int rr = 0; rr < nr; ++rr) {
+                double *dst = Et + (int64_t)(c * Nfp + a0 + rr) * ld;
+                const double *out = sOut[rr];
+                for (int col = tid; col < ld; col += blockDim.x) {
+                    const int idx = sMap[col];
+                    dst[col] = idx >= 0 ? out[idx] : 0.0;
+                }
             }
         }
     }
