@@ -630,8 +630,27 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
     }
     __syncthreads();
     if (backsub) {
+        // left-looking by 64-row blocks from the bottom: a block's rows first take
+        // the solved part, y[r] -= U[r][i1:n] x[i1:n] (one dot product per row,
+        // kRQ rows per wave), then wave 0 solves the diagonal block
         for (int i1 = n; i1 > 0; i1 -= kRB) {
             const int i0 = max(0, i1 - kRB), nb = i1 - i0;
+            for (int r = i0 + kRQ * wave; r < i1; r += kRQ * kRW) {
+                double acc[kRQ];
+#pragma unroll
+                for (int q = 0; q < kRQ; ++q) acc[q] = 0.0;
+                for (int c = i1 + lane; c < n; c += 64) {
+                    const double xc = sy[c];
+#pragma unroll
+                    for (int q = 0; q < kRQ; ++q)
+                        if (r + q < i1) acc[q] += E[(int64_t)(r + q) * ld + c] * xc;
+                }
+#pragma unroll
+                for (int q = 0; q < kRQ; ++q) {
+                    const double t = wave_sum(acc[q]);
+                    if (lane == 0 && r + q < i1) sy[r + q] -= t;
+                }
+            }
             for (int t = threadIdx.x; t < kRB * kRB; t += blockDim.x) {
                 const int r = t / kRB, c = t % kRB;
                 sU[r][c] = (r < nb && c < nb) ? E[(int64_t)(i0 + r) * ld + i0 + c] : 0.0;
@@ -646,20 +665,6 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
                     else if (lane < c) yl -= sU[lane][c] * xc;
                 }
                 if (lane < nb) sy[i0 + lane] = yl;
-            }
-            __syncthreads();
-            // rows above: y[r] -= U[r][i0:i1] x[i0:i1], lane c takes column i0 + c
-            const double xl = (lane < nb) ? sy[i0 + lane] : 0.0;
-            for (int r = kRQ * wave; r < i0; r += kRQ * kRW) {
-                double v[kRQ];
-#pragma unroll
-                for (int q = 0; q < kRQ; ++q)
-                    v[q] = (r + q < i0 && lane < nb) ? E[(int64_t)(r + q) * ld + i0 + lane] * xl : 0.0;
-#pragma unroll
-                for (int q = 0; q < kRQ; ++q) {
-                    const double t = wave_sum(v[q]);
-                    if (lane == 0 && r + q < i0) sy[r + q] -= t;
-                }
             }
             __syncthreads();
         }
