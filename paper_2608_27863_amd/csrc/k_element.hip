@@ -464,6 +464,8 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
     __shared__ double sV[2][p1 * p1 * p1][nq];   // y stage of one i1 slice
     __shared__ double sF[kSF];                   // face terms / trace-column blocks
     __shared__ double sG[kSG];                   // first stage of the 2-D contractions
+    constexpr int kNqfFace = kNQ * kNQ;          // Gauss points of a face, at most
+    __shared__ double sCf[6][kNqfFace];          // one block's face coefficients
     __shared__ unsigned char sNm[Np];            // faces each node lies on (bit lf)
     __shared__ unsigned char sNa[6][Np];         // its face-local index a0 p1 + a1 there
     for (int t = tid; t < p1 * nq; t += blockDim.x) {
@@ -578,6 +580,12 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
             __syncthreads();
             for (int t = tid; t < 4 * Nq; t += blockDim.x)
                 sC[t / Nq][t % Nq] = qpe[(int64_t)(4 * (20 * c + sblk) + t / Nq) * Nq + t % Nq];
+            // the block's face coefficients at each face's Gauss points
+            for (int t = tid; t < 6 * kNqfFace; t += blockDim.x) {
+                const int lf = t / kNqfFace, sq = t % kNqfFace;
+                if (sq < sNqf[lf]) sCf[lf][sq] = qpe[sFbase[lf] + (int64_t)(25 * c + slot) * sNqf[lf] + sq];
+            }
+            __syncthreads();
             // face terms: F[a0 a1][b0 b1] = sum_s c(s) phi_a(s) phi_b(s) per face, two 1-D stages
             for (int t = tid; t < 6 * p1 * p1 * kNQ; t += blockDim.x) {
                 const int lf = t / (p1 * p1 * kNQ), rem = t % (p1 * p1 * kNQ);
@@ -585,7 +593,7 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
                 const int nqf1 = sPf[lf] + 2;
                 double v = 0.0;
                 if (s1 < nqf1) {
-                    const double *cf = qpe + sFbase[lf] + (int64_t)(25 * c + slot) * sNqf[lf];
+                    const double *cf = sCf[lf];
                     for (int s0 = 0; s0 < nqf1; ++s0)
                         v += sLf[lf][a0 * nqf1 + s0] * sLf[lf][b0 * nqf1 + s0] * cf[s0 + nqf1 * s1];
                 }
