@@ -79,7 +79,7 @@ constexpr int kW = 8;         // register sub-panel width
 constexpr int kHalf = 32;     // the panel is factored as two halves (sub-panels update only within a half)
 constexpr int kPT = 512;      // panel kernel threads
 constexpr int kRPC = 32;      // columns per k_rowperm workgroup
-constexpr int kBC = 32;       // columns per k_blocku workgroup
+constexpr int kBC = 64;       // columns per k_blocku workgroup
 constexpr int kCR = 128;      // trace rows per k_crows workgroup
 static_assert(kW >= 8 && kPT >= 2 * 64, "panel scratch and permutation assumptions");
 // A recorded permutation of w swaps (row base+jj <-> piv[jj]): [0] = number of
@@ -898,7 +898,7 @@ __global__ void __launch_bounds__(256) k_inv128(DevMesh dm, SysDesc sd, int e0, 
     triple(2 * kNB * kNB, k0, k0 + kNB, false, 3 * kNB * kNB, kWsUc);    // Uc = -Ua^{-1} U_ab Ub^{-1}
 }
 
-// One 32-column tile of a block of nrows = min(128, n - k0) pivot columns
+// One kBC-column tile of a block of nrows = min(128, n - k0) pivot columns
 // applied to other columns: X = P A12 (the block's net row permutation: permuted
 // top rows gathered into LDS, displaced rows moved), then U12 = L11^{-1} X in a
 // single product with the recorded inverse.  The zero blocks of the triangle
