@@ -179,6 +179,16 @@ int hdg_layout(const hdg_ctx *ctx, int kind, int64_t *dst, int64_t capacity);
 /* Length of a layout array (so the caller can size dst). */
 int64_t hdg_layout_length(const hdg_ctx *ctx, int kind);
 
+/* Block-sparse pattern of the assembled trace operator S of eq. schur-trace
+ * (section 3.2): face F's row holds one block per face G that shares an element
+ * with F.  *nnzb receives the number of blocks; *row_ptr_dev a device array of
+ * int32 [n_face+1], *col_dev a device array of int32 [nnzb] (ascending G within
+ * a row): the same values as HDG_LAYOUT_BSR_ROW_PTR and HDG_LAYOUT_BSR_COL.  The
+ * arrays belong to the context, are read-only and stay valid until hdg_destroy.
+ * Any output pointer may be NULL.  No device work; HDG_ERR_INVALID_ARGUMENT
+ * for a null context. */
+int hdg_bsr_pattern(const hdg_ctx *ctx, int *nnzb, const int **row_ptr_dev, const int **col_dev);
+
 /* Workspace sizes in bytes (caller allocates, 256-byte aligned).  `op` is the
  * entry point: 0 hdg_local_residual_jacobian and 1 hdg_condense (for a chunk
  * of ne elements starting at e0), 2 hdg_asm_setup, 3 hdg_asm_block_apply,

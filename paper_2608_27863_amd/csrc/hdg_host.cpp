@@ -579,6 +579,14 @@ int hdg_layout(const hdg_ctx *ctx, int kind, int64_t *dst, int64_t capacity) {
     return HDG_OK;
 }
 
+int hdg_bsr_pattern(const hdg_ctx *ctx, int *nnzb, const int **row_ptr_dev, const int **col_dev) {
+    if (!ctx) return HDG_ERR_INVALID_ARGUMENT;
+    if (nnzb) *nnzb = (int)ctx->bsr_col.size();
+    if (row_ptr_dev) *row_ptr_dev = ctx->dm.bsr_row_ptr;
+    if (col_dev) *col_dev = ctx->dm.bsr_col;
+    return HDG_OK;
+}
+
 static bool chunk_ok(const hdg_ctx *ctx, int e0, int ne) {
     return ctx && e0 >= 0 && ne >= 1 && (int64_t)e0 + ne <= ctx->n_elem;
 }

@@ -23,7 +23,7 @@ HDG_MIXED_FAST = 2  # all-FP32 condensation, reported beside HDG_MIXED
 LAYOUT = {"node_off": 0, "face_off": 1, "E_off": 2, "SK_off": 3, "bsr_row_ptr": 4, "bsr_col": 5,
           "bsr_val_off": 6, "asm_off": 7, "elem_n": 8, "elem_f": 9, "x_off": 10}
 
-EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_layout_length",
+EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_layout_length", "hdg_bsr_pattern",
            "hdg_workspace_size", "hdg_local_residual_jacobian", "hdg_condense", "hdg_assemble_trace",
            "hdg_face_matvec", "hdg_asm_setup", "hdg_asm_block_apply", "hdg_gmres", "hdg_recover_interior",
            "hdg_store_x", "hdg_recover_interior_x",
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     L.hdg_layout.argtypes = [_vp, _i, _vp, ctypes.c_int64]
     L.hdg_layout_length.argtypes = [_vp, _i]
     L.hdg_layout_length.restype = ctypes.c_int64
+    L.hdg_bsr_pattern.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]
     L.hdg_workspace_size.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]
     L.hdg_local_residual_jacobian.argtypes = [_vp, _i, _i] + [_vp] * 7 + [_vp, ctypes.c_size_t, _vp]
     L.hdg_condense.argtypes = [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -209,6 +210,13 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def hdg_bsr_pattern(self):
+        """(nnzb, device address of row_ptr int32[n_face+1], device address of col int32[nnzb])."""
+        nnzb, rp, col = _i(), _vp(), _vp()
+        _check(self.L.hdg_bsr_pattern(self.h, ctypes.byref(nnzb), ctypes.byref(rp), ctypes.byref(col)),
+               "hdg_bsr_pattern")
+        return nnzb.value, rp.value, col.value
 
     # ------------------------------------------------------------- sizes
     def workspace_size(self, op, prec=HDG_FP64, e0=0, ne=None):

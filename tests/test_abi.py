@@ -75,4 +75,5 @@ def test_entry_points_reject_null_context():
     assert L.hdg_recover_interior(None, 0, 0, 1, None, None, None, None) == -1
     assert L.hdg_asm_block_apply(None, 0, None, None, None, None, 0, None) == -1
     assert L.hdg_local_residual_jacobian(None, 0, 1, *([None] * 8), 0, None) == -1
+    assert L.hdg_bsr_pattern(None, None, None, None) == -1
     assert L.hdg_status_string(-5) == b"workspace too small"

@@ -169,3 +169,33 @@ def test_argument_errors_reach_no_kernel():
         st.ctx.hdg_face_matvec(st.S, st.g, st.g)                                 # aliasing
     with pytest.raises(hdg.HDGError, match="invalid argument"):
         st.ctx.hdg_gmres(0, st.S, st.Sinv, st.g, 0, st.dUhat, st.hist, st.gm_work)  # m = 0
+
+
+def test_bsr_pattern_on_device():
+    """hdg_bsr_pattern hands out the context's device copy of the pattern of S:
+    equal to the host layout, and row F holds exactly the faces that share an
+    element with F (eq. schur-trace), ascending."""
+    import ctypes
+    from paper_2608_27863_amd import hdg
+    wl = _wl_walls()
+    mesh = wl.mesh
+    ctx = hdg.Context(mesh, wl)
+    try:
+        nnzb, rp_dev, col_dev = ctx.hdg_bsr_pattern()
+        print(f"[bsr] {mesh.n_face} faces, {nnzb} blocks", flush=True)
+        assert nnzb == len(ctx.layout["bsr_col"]) and rp_dev and col_dev
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        rp = np.zeros(mesh.n_face + 1, dtype=np.int32)
+        col = np.zeros(nnzb, dtype=np.int32)
+        assert hip.hipMemcpy(rp.ctypes.data, rp_dev, rp.nbytes, 2) == 0  # device to host
+        assert hip.hipMemcpy(col.ctypes.data, col_dev, col.nbytes, 2) == 0
+        assert np.array_equal(rp, ctx.layout["bsr_row_ptr"]) and np.array_equal(col, ctx.layout["bsr_col"])
+        for F in range(mesh.n_face):
+            elems = {int(mesh.face_elem[F, s, 0]) for s in range(2) if mesh.face_elem[F, s, 0] >= 0}
+            want = sorted({int(G) for e in elems for G in mesh.elem_face[e]})
+            assert list(col[rp[F]:rp[F + 1]]) == want, F
+        only = ctypes.c_int(-7)
+        assert ctx.L.hdg_bsr_pattern(ctx.h, ctypes.byref(only), None, None) == 0 and only.value == nnzb
+    finally:
+        ctx.close()
