@@ -189,6 +189,24 @@ int64_t hdg_layout_length(const hdg_ctx *ctx, int kind);
  * for a null context. */
 int hdg_bsr_pattern(const hdg_ctx *ctx, int *nnzb, const int **row_ptr_dev, const int **col_dev);
 
+/* Attainable peaks, for roofline fractions against what this chip reaches
+ * beside its datasheet figures (measurement helpers, not steps of the method).
+ * hdg_peak_mfma: n_wg (1 .. 1048576) workgroups of 256 threads; each of their
+ * waves issues iters (>= 1) x 8 independent 16x16x4 matrix-core products from
+ * register operands equal to `one`, FP64 for fp_bits = 64, FP32 for 32:
+ * n_wg * 4 * iters * 8 * 2048 flop per call.  sink: device, n_wg * 256 values
+ * of that type, caller-owned; each receives 128 * iters * one^2 (exact for
+ * one = 1 while 4 * iters < 2^24 in FP32).  hdg_peak_read: reads `bytes` (a
+ * positive multiple of 16) from src (device, 16-byte aligned) and XORs every
+ * 32-bit word into *sink (device, one uint32 the caller zeroes first).
+ * hdg_peak_copy: copies `bytes` (a positive multiple of 16) from src to dst
+ * (device, 16-byte aligned, not overlapping): 2 * bytes of memory traffic.
+ * All are asynchronous on `stream`; HDG_ERR_INVALID_ARGUMENT for other
+ * arguments. */
+int hdg_peak_mfma(int fp_bits, int n_wg, int iters, double one, void *sink, void *stream);
+int hdg_peak_read(const void *src, size_t bytes, unsigned *sink, void *stream);
+int hdg_peak_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* Workspace sizes in bytes (caller allocates, 256-byte aligned).  `op` is the
  * entry point: 0 hdg_local_residual_jacobian and 1 hdg_condense (for a chunk
  * of ne elements starting at e0), 2 hdg_asm_setup, 3 hdg_asm_block_apply,

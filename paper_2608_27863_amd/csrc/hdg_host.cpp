@@ -661,6 +661,24 @@ int hdg_assemble_trace(hdg_ctx *ctx, const double *SK, double *S_bsr, double *g,
     return dev_status(hdg::launch_assemble(ctx, SK, S_bsr, g, (hipStream_t)stream));
 }
 
+int hdg_peak_mfma(int fp_bits, int n_wg, int iters, double one, void *sink, void *stream) {
+    if ((fp_bits != 64 && fp_bits != 32) || n_wg < 1 || n_wg > (1 << 20) || iters < 1 || !sink)
+        return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_peak_mfma(fp_bits, n_wg, iters, one, sink, (hipStream_t)stream));
+}
+
+int hdg_peak_read(const void *src, size_t bytes, unsigned *sink, void *stream) {
+    if (!src || !sink || bytes == 0 || bytes % 16 || (uintptr_t)src % 16) return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_peak_read(src, bytes, sink, (hipStream_t)stream));
+}
+
+int hdg_peak_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    if (!src || !dst || bytes == 0 || bytes % 16 || a % 16 || b % 16 || (a < b + bytes && b < a + bytes))
+        return HDG_ERR_INVALID_ARGUMENT;
+    return dev_status(hdg::launch_peak_copy(src, dst, bytes, (hipStream_t)stream));
+}
+
 int hdg_face_matvec(hdg_ctx *ctx, const double *S_bsr, const double *x, double *y, void *stream) {
     if (!ctx || !S_bsr || !x || !y || x == y) return HDG_ERR_INVALID_ARGUMENT;
     return dev_status(hdg::launch_matvec(ctx, S_bsr, x, y, (hipStream_t)stream));

@@ -133,6 +133,10 @@ size_t bordered_lu_work(const hdg_ctx *ctx, int ne);
 int run_asm_inversion(const hdg_ctx *ctx, int prec, void *sys, int *info, void *work, hipStream_t s);
 int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, hipStream_t s);
 int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *y, hipStream_t s);
+// attainable-peak probes (k_peak.hip)
+int launch_peak_mfma(int fp_bits, int n_wg, int iters, double one, void *sink, hipStream_t s);
+int launch_peak_read(const void *src, size_t bytes, unsigned *sink, hipStream_t s);
+int launch_peak_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, int *info,
                      void *work, hipStream_t s);
 size_t asm_setup_work_bytes(const hdg_ctx *ctx, int prec);

@@ -30,7 +30,7 @@ EXPORTS = ["hdg_create", "hdg_destroy", "hdg_status_string", "hdg_layout", "hdg_
            "hdg_newton_step", "hdg_graph_capture_newton", "hdg_graph_launch", "hdg_graph_destroy",
            "hdg_asm_block_apply_noalloc", "hdg_gmres_x0", "hdg_rb_guess", "hdg_rb_insert", "hdg_state_update",
            "hdg_state_admissible", "hdg_lincomb", "hdg_residual_gather", "hdg_residual_norm", "hdg_av_field",
-           "hdg_set_update_tile", "hdg_get_update_tile"]
+           "hdg_set_update_tile", "hdg_get_update_tile", "hdg_peak_mfma", "hdg_peak_read", "hdg_peak_copy"]
 
 RB_MAX = 32
 
@@ -118,6 +118,9 @@ def load_library(path: str = LIB_PATH):
     L.hdg_av_field.argtypes = [_vp, ctypes.POINTER(_AvParams), _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.hdg_set_update_tile.argtypes = [_vp, _i, _i]
     L.hdg_get_update_tile.argtypes = [_vp, _i]
+    L.hdg_peak_mfma.argtypes = [_i, _i, _i, ctypes.c_double, _vp, _vp]
+    L.hdg_peak_read.argtypes = [_vp, ctypes.c_size_t, _vp, _vp]
+    L.hdg_peak_copy.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
     for name in EXPORTS:
         if name not in ("hdg_destroy", "hdg_status_string", "hdg_layout_length", "hdg_graph_destroy"):
             getattr(L, name).restype = _i
@@ -151,6 +154,33 @@ def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def hdg_peak_mfma(fp_bits, n_wg, iters, one, sink, stream=None):
+    """Matrix-core peak probe (no context): n_wg * 4 * iters * 8 * 2048 flop."""
+    import torch
+    dt = torch.float64 if fp_bits == 64 else torch.float32
+    L = load_library()
+    _check(L.hdg_peak_mfma(fp_bits, n_wg, iters, float(one), _ptr(sink, dt, n_wg * 256, "sink"), _stream(stream)),
+           "hdg_peak_mfma")
+
+
+def hdg_peak_read(src, sink, stream=None):
+    """Streaming-read probe (no context): XOR of src's 32-bit words into sink[0] (int32, zeroed by the caller)."""
+    import torch
+    L = load_library()
+    _check(L.hdg_peak_read(_ptr(src, None, None, "src"), src.numel() * src.element_size(),
+                           _ptr(sink, torch.int32, 1, "sink"), _stream(stream)), "hdg_peak_read")
+
+
+def hdg_peak_copy(src, dst, stream=None):
+    """Streaming-copy probe (no context): copies src into dst, 2 * bytes of traffic."""
+    L = load_library()
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise HDGError("dst is smaller than src")
+    _check(L.hdg_peak_copy(_ptr(src, None, None, "src"), _ptr(dst, None, None, "dst"), nbytes, _stream(stream)),
+           "hdg_peak_copy")
 
 
 def descriptors(mesh, wl_or_phys):
