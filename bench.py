@@ -129,12 +129,15 @@ def measure_peaks(torch, hdg):
 
 
 def matvec_bytes(ctx):
-    """Algorithmic bytes of y = S x: S read once, block-sparse indices, x read
-    once, y written once."""
+    """Algorithmic bytes of y = S x: S's blocks read once (not the padding that
+    starts each block on a 128-byte line), block-sparse indices, x read once, y
+    written once."""
     import numpy as np
-    vo = ctx.layout["bsr_val_off"]
-    nnzb = len(ctx.layout["bsr_col"])
-    return 8.0 * float(vo[-1]) + 4.0 * nnzb + 4.0 * (ctx.n_face + 1) + 2.0 * 8.0 * ctx.N_uh
+    rp, col, fo = (ctx.layout[k] for k in ("bsr_row_ptr", "bsr_col", "face_off"))
+    b = np.diff(fo).astype(np.float64)
+    rows = np.repeat(np.arange(ctx.n_face), np.diff(rp))
+    s_entries = float(np.sum(b[rows] * b[col]))
+    return 8.0 * s_entries + 4.0 * len(col) + 4.0 * (ctx.n_face + 1) + 2.0 * 8.0 * ctx.N_uh
 
 
 def host_cpu():

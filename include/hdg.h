@@ -60,7 +60,10 @@
  * - Assembled trace operator S: block-sparse rows, one block row per face,
  *   block (F, F') of size (5 N_fp(F)) x (5 N_fp(F')) stored column-major at
  *   bsr_val_off[k] for k in bsr_row_ptr[F] .. bsr_row_ptr[F+1]-1, column
- *   face bsr_col[k] (ascending).  Pattern built by hdg_create.
+ *   face bsr_col[k] (ascending).  Pattern built by hdg_create.  Every
+ *   bsr_val_off[k] is a multiple of 16 (blocks start on 128-byte lines); the
+ *   entries between a block's end and the next offset are zero after
+ *   hdg_assemble_trace.
  * - Layout arrays are obtained with hdg_layout().
  */
 #ifndef HDG_H

@@ -421,7 +421,9 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
         for (size_t k = 0; k < cols[F].size(); ++k) {
             int kk = ctx->bsr_row_ptr[F] + (int)k, G = cols[F][k];
             ctx->bsr_col[kk] = G;
-            ctx->bsr_val_off[kk + 1] = ctx->bsr_val_off[kk] + (int64_t)trace_size(ctx->face_p[F]) * trace_size(ctx->face_p[G]);
+            // every block starts on a 128-byte line (16 doubles): the matvec streams whole lines
+            const int64_t sz = (int64_t)trace_size(ctx->face_p[F]) * trace_size(ctx->face_p[G]);
+            ctx->bsr_val_off[kk + 1] = (ctx->bsr_val_off[kk] + sz + 15) / 16 * 16;
         }
     auto blk_index = [&](int F, int G) {
         auto b = ctx->bsr_col.begin() + ctx->bsr_row_ptr[F], en = ctx->bsr_col.begin() + ctx->bsr_row_ptr[F + 1];

@@ -36,6 +36,9 @@ __global__ void __launch_bounds__(256) k_assemble_blocks(DevMesh dm, const doubl
         }
         out[t] = v;
     }
+    // the block's padding up to the next 128-byte line
+    const int pad_end = (int)(dm.bsr_val_off[k + 1] - dm.bsr_val_off[k]);
+    for (int t = bF * bG + threadIdx.x; t < pad_end; t += blockDim.x) out[t] = 0.0;
 }
 
 __global__ void __launch_bounds__(128) k_assemble_g(DevMesh dm, const double *__restrict__ SK, double *__restrict__ g) {
@@ -56,24 +59,27 @@ __global__ void __launch_bounds__(128) k_assemble_g(DevMesh dm, const double *__
 
 // -------------------------------------------------------------------- matvec
 constexpr int kMaxRowBlocks = 16;
+constexpr int kMvPiece = 4096;  // doubles of a block staged in LDS at a time (32 KB)
 
-// One workgroup per face row; its 256 threads read each block's columns as one
-// contiguous run.  NT: streaming (nontemporal) loads, the choice when every
-// block column is whole 128-byte lines; otherwise columns share lines with
-// their neighbours, read by other waves, and plain loads let L2 serve the
-// second read (streaming loads fetched those lines twice: 1.19x the bytes of
-// S at p = 4, where a column is 1000 bytes).
-template <bool NT>
+// One workgroup per face row F.  Each block (column-major bF x bG, starting on
+// a 128-byte line, zero padding after it) is streamed through LDS in pieces of
+// kMvPiece doubles, every thread with eight nontemporal 16-byte loads in flight
+// over the piece's contiguous range, so every line is read once and whole.
+// Thread (i, w) owns row i (i = tid mod bF, w = tid div bF < W = 256 div bF)
+// and sums S[i][j] x[j] over its columns j = w mod W in increasing j; the W
+// partial sums are added in order of w, so the result does not depend on
+// timing.
 __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__restrict__ S,
                                                 const double *__restrict__ x, double *__restrict__ y) {
-    auto ld = [](const double *p) { return NT ? __builtin_nontemporal_load(p) : *p; };
     const int F = blockIdx.x;
     const int bF = (int)(dm.face_off[F + 1] - dm.face_off[F]);
     const int k0 = dm.bsr_row_ptr[F], nk = dm.bsr_row_ptr[F + 1] - k0;
+    const int tid = threadIdx.x;
+    __shared__ __attribute__((aligned(16))) double sp[kMvPiece];
     __shared__ double sx[kMaxRowBlocks * 125];
     __shared__ int sxo[kMaxRowBlocks + 1];
     __shared__ double sred[256];
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         int o = 0;
         for (int q = 0; q < nk; ++q) {
             sxo[q] = o;
@@ -86,37 +92,53 @@ __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__rest
     for (int q = 0; q < nk; ++q) {
         const int G = dm.bsr_col[k0 + q];
         const int bG = sxo[q + 1] - sxo[q];
-        for (int t = threadIdx.x; t < bG; t += blockDim.x) sx[sxo[q] + t] = x[dm.face_off[G] + t];
+        for (int t = tid; t < bG; t += blockDim.x) sx[sxo[q] + t] = x[dm.face_off[G] + t];
     }
-    __syncthreads();
     const int W = 256 / bF;
-    const int i = threadIdx.x % bF, w = threadIdx.x / bF;
+    const int i = tid % bF, w = tid / bF;
     double acc = 0.0;
-    if (w < W) {
-        for (int q = 0; q < nk; ++q) {
-            const double *blk = S + dm.bsr_val_off[k0 + q];
-            const double *xs = sx + sxo[q];
-            const int bG = sxo[q + 1] - sxo[q];
-            int j = w;
-            for (; j + 3 * W < bG; j += 4 * W) {
-                const double a0 = ld(blk + i + (int64_t)j * bF);
-                const double a1 = ld(blk + i + (int64_t)(j + W) * bF);
-                const double a2 = ld(blk + i + (int64_t)(j + 2 * W) * bF);
-                const double a3 = ld(blk + i + (int64_t)(j + 3 * W) * bF);
-                acc += a0 * xs[j];
-                acc += a1 * xs[j + W];
-                acc += a2 * xs[j + 2 * W];
-                acc += a3 * xs[j + 3 * W];
+    for (int q = 0; q < nk; ++q) {
+        const double *blk = S + dm.bsr_val_off[k0 + q];
+        const double *xs = sx + sxo[q];
+        const int bG = sxo[q + 1] - sxo[q], n = bF * bG;
+        for (int p0 = 0; p0 < n; p0 += kMvPiece) {
+            const int len = min(kMvPiece, n - p0);
+            const int units = (len + 1) / 2;  // an odd block's last unit takes one zero of the padding
+            v2d v[kMvPiece / 2 / 256];
+#pragma unroll
+            for (int r = 0; r < kMvPiece / 2 / 256; ++r) {
+                const int u = tid + 256 * r;
+                if (u < units) v[r] = __builtin_nontemporal_load((const v2d *)(blk + p0) + u);
             }
-            for (; j < bG; j += W) acc += ld(blk + i + (int64_t)j * bF) * xs[j];
+            __syncthreads();  // the previous piece has been read (and, first, sx is complete)
+#pragma unroll
+            for (int r = 0; r < kMvPiece / 2 / 256; ++r) {
+                const int u = tid + 256 * r;
+                if (u < units) *(v2d *)(sp + 2 * u) = v[r];
+            }
+            __syncthreads();
+            if (w < W) {
+                // columns j with j bF + i in [p0, p0 + len) and j = w mod W
+                const int jlo = (p0 > i) ? (p0 - i + bF - 1) / bF : 0;
+                const int last = p0 + len - 1 - i;
+                const int jhi = last >= 0 ? last / bF : -1;
+                int j = jlo + ((w - jlo % W) + W) % W;
+                for (; j + 3 * W <= jhi; j += 4 * W) {
+                    acc += sp[j * bF + i - p0] * xs[j];
+                    acc += sp[(j + W) * bF + i - p0] * xs[j + W];
+                    acc += sp[(j + 2 * W) * bF + i - p0] * xs[j + 2 * W];
+                    acc += sp[(j + 3 * W) * bF + i - p0] * xs[j + 3 * W];
+                }
+                for (; j <= jhi; j += W) acc += sp[j * bF + i - p0] * xs[j];
+            }
         }
     }
-    sred[threadIdx.x] = acc;
+    sred[tid] = acc;
     __syncthreads();
-    if (threadIdx.x < bF) {
+    if (tid < bF) {
         double v = 0.0;
-        for (int ww = 0; ww < W; ++ww) v += sred[ww * bF + threadIdx.x];
-        y[dm.face_off[F] + threadIdx.x] = v;
+        for (int ww = 0; ww < W; ++ww) v += sred[ww * bF + tid];
+        y[dm.face_off[F] + tid] = v;
     }
 }
 
@@ -709,10 +731,7 @@ int launch_assemble(const hdg_ctx *ctx, const double *SK, double *S, double *g, 
 }
 
 int launch_matvec(const hdg_ctx *ctx, const double *S, const double *x, double *y, hipStream_t s) {
-    if (ctx->face_cols_aligned)
-        hipLaunchKernelGGL(k_matvec<true>, dim3(ctx->n_face), dim3(256), 0, s, ctx->dm, S, x, y);
-    else
-        hipLaunchKernelGGL(k_matvec<false>, dim3(ctx->n_face), dim3(256), 0, s, ctx->dm, S, x, y);
+    hipLaunchKernelGGL(k_matvec, dim3(ctx->n_face), dim3(256), 0, s, ctx->dm, S, x, y);
     return (int)hipGetLastError();
 }
 

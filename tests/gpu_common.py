@@ -56,7 +56,7 @@ def bsr_blocks(ctx, Shost):
         for k in range(int(rp[F]), int(rp[F + 1])):
             G = int(col[k])
             bG = int(fo[G + 1] - fo[G])
-            out[(F, G)] = Shost[int(vo[k]):int(vo[k + 1])].reshape(bG, bF).T
+            out[(F, G)] = Shost[int(vo[k]):int(vo[k]) + bF * bG].reshape(bG, bF).T
     return out
 
 
