@@ -12,7 +12,9 @@
 //       coefficients with the basis (phi_i, reference derivatives of phi_i,
 //       phi_k, trace basis mu_a) into the rows of the element system
 //       E^K = [[A B R_qu],[C D R_uh]], by sum factorisation over the tensor
-//       Gauss points.
+//       Gauss points.  Their bulk stores are nontemporal: a chunk's systems
+//       (21.7 GB for 256 elements at p = 4) are far larger than any cache, so
+//       keeping the written lines only evicts other data.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -551,7 +553,7 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
                         v += sF[lf * p1 * p1 * p1 * p1 + sNa[lf][irow] * p1 * p1 + sNa[lf][k]];
                     }
                 }
-                Er[(int64_t)(i1 + p1 * q) * ld + sblk * Np + k] = v;
+                __builtin_nontemporal_store(v, Er + (int64_t)(i1 + p1 * q) * ld + sblk * Np + k);
             }
         }
     };
@@ -562,7 +564,7 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
         // component c) over their columns; volume_block begins with a barrier
         const v2d zero2 = {0.0, 0.0};
         for (int t = tid; t < Np * (n / 2); t += blockDim.x)
-            *(v2d *)(Er + (int64_t)(t / (n / 2)) * ld + 2 * (t % (n / 2))) = zero2;
+            __builtin_nontemporal_store(zero2, (v2d *)(Er + (int64_t)(t / (n / 2)) * ld + 2 * (t % (n / 2))));
         for (int kind = 0; kind < 2; ++kind) {
             __syncthreads();
             for (int t = tid; t < 4 * Nq; t += blockDim.x) {
@@ -649,7 +651,7 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
             const double *fc = sF + cp * p1 * p1 * Nfp + b;
             double *dst = Er + n + toff[lf] + col;
             for (int i = tid / ncol; i < Np; i += groups)
-                dst[(int64_t)i * ld] = ((sNm[i] >> lf) & 1u) ? fc[sNa[lf][i] * Nfp] : 0.0;
+                __builtin_nontemporal_store(((sNm[i] >> lf) & 1u) ? fc[sNa[lf][i] * Nfp] : 0.0, dst + (int64_t)i * ld);
         }
     }
     // ---- residual column and padding: the residual's point coefficients in LDS,
@@ -800,7 +802,7 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
                 const double *out = sOut[rr];
                 for (int col = tid; col < ld; col += blockDim.x) {
                     const int idx = sMap[col];
-                    dst[col] = idx >= 0 ? out[idx] : 0.0;
+                    __builtin_nontemporal_store(idx >= 0 ? out[idx] : 0.0, dst + col);
                 }
             }
         }
