@@ -869,11 +869,9 @@ static int newton_enqueue(hdg_ctx *ctx, const hdg_newton_args *a, void *stream) 
     if ((rc = hdg_gmres(ctx, a->asm_prec, a->S_bsr, a->Sinv, a->g, a->gmres_m, a->dUhat, a->res_hist,
                         a->gmres_work, a->gmres_work_bytes, stream)))
         return rc;
-    for (int k = 0; k < a->n_chunks; ++k) {
-        const int e0 = a->chunk_e0[k], ne = a->chunk_ne[k];
-        if ((rc = hdg_recover_interior(ctx, a->prec, e0, ne, Ek(e0), a->dUhat, a->dQU, stream))) return rc;
-    }
-    return HDG_OK;
+    // every system is resident: one recovery launch over all elements keeps several
+    // workgroups per CU busy on the sequential block steps of the back substitution
+    return hdg_recover_interior(ctx, a->prec, 0, ctx->n_elem, a->E, a->dUhat, a->dQU, stream);
 }
 
 int hdg_set_update_tile(hdg_ctx *ctx, int n, int tile_rows) {

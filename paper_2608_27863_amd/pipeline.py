@@ -131,8 +131,9 @@ class NewtonStep:
         if self.stream_E:
             self.ctx.hdg_recover_interior_x(0, self.ctx.n_elem, self.X, self.dUhat, self.dQU, stream)
             return
-        for e0, n in self.chunks:
-            self.ctx.hdg_recover_interior(self.prec, e0, n, self.E_chunk(e0, n), self.dUhat, self.dQU, stream)
+        # every system is resident: one launch over all elements (each element's
+        # recovery is independent, so this equals the per-chunk calls bit for bit)
+        self.ctx.hdg_recover_interior(self.prec, 0, self.ctx.n_elem, self.E, self.dUhat, self.dQU, stream)
 
     def run(self, stream=None):
         """The whole hot path for one Newton step, as one call (hdg_newton_step)."""
