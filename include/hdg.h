@@ -171,7 +171,9 @@ typedef enum {
     HDG_LAYOUT_BSR_ROW_PTR = 4, /* [n_face+1]                                         */
     HDG_LAYOUT_BSR_COL = 5,     /* [nnzb]                                             */
     HDG_LAYOUT_BSR_VAL_OFF = 6, /* [nnzb+1] block offsets (doubles)                   */
-    HDG_LAYOUT_ASM_OFF = 7,     /* [n_elem+1] Schwarz block offsets (entries)          */
+    HDG_LAYOUT_ASM_OFF = 7,     /* [n_elem+1] Schwarz block offsets (entries, multiples
+                                   of 32: blocks start on 128-byte lines; the entries
+                                   between blocks are zero after hdg_asm_setup)        */
     HDG_LAYOUT_ELEM_N = 8,      /* [n_elem] n_e                                       */
     HDG_LAYOUT_ELEM_F = 9,      /* [n_elem] f_e                                       */
     HDG_LAYOUT_X_OFF = 10       /* [n_elem+1] retained-X offsets (doubles): element e's

@@ -331,7 +331,7 @@ int hdg_create(const hdg_mesh_desc *m, const hdg_phys *phys, hdg_ctx **out) {
         ctx->node_off[e + 1] = ctx->node_off[e] + Np;
         ctx->E_off[e + 1] = ctx->E_off[e] + (int64_t)(n + f) * hdg::e_ld(n, f);
         ctx->SK_off[e + 1] = ctx->SK_off[e] + (int64_t)f * (f + 1);
-        ctx->asm_off[e + 1] = ctx->asm_off[e] + (int64_t)f * f;
+        ctx->asm_off[e + 1] = (ctx->asm_off[e] + (int64_t)f * f + 31) / 32 * 32;  // blocks start on 128-byte lines
         ctx->qp_off[e + 1] = ctx->qp_off[e] + (int64_t)(hdg::kVJac + hdg::kVRes) * Nq + (int64_t)hdg::kFPer * nqf_tot;
         ctx->vgeo_off[e + 1] = ctx->vgeo_off[e] + 10 * Nq;
         const int fe = hdg::asm_pad(f);  // Schwarz system size

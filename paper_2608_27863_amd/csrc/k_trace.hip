@@ -208,6 +208,10 @@ __global__ void __launch_bounds__(256) k_asm_extract(DevMesh dm, const T *__rest
         const int j = j0 + c, i = i0 + tx;
         if (i < f && j < f) out[(int64_t)j * f + i] = tile[tx][c];
     }
+    if (blockIdx.x == 0 && blockIdx.y == 0) {  // the block's padding up to the next 128-byte line
+        const int64_t pad_end = dm.asm_off[e + 1] - dm.asm_off[e];
+        for (int64_t t = (int64_t)f * f + threadIdx.x; t < pad_end; t += blockDim.x) out[t] = T(0);
+    }
 }
 
 // ------------------------------------------------------------- Schwarz apply
@@ -244,52 +248,67 @@ __global__ void __launch_bounds__(256) k_asm_local(DevMesh dm, const T *__restri
     zloc[dm.tloc_off[e] + i] = acc;
 }
 
-// The same product with one workgroup per element: each thread owns rows i,
-// i + 256, i + 512 (f <= 768), so every column of the inverse is read by one
-// workgroup, on one CU and one XCD's L2.  Used when the columns do not start
-// on 128-byte lines: a line shared by two columns is then read twice by the
-// same workgroup instead of by two workgroups on different XCDs (which fetch
-// it twice).  The sum runs over j in the same order as in k_asm_local, so the
-// two give identical results.
+// The same product with one workgroup per element, for inverses whose columns
+// do not start on 128-byte lines (f <= 768).  The element's block (starting on a
+// line, zero padding after it) streams through LDS in 32 KB pieces with
+// nontemporal 16-byte loads, eight in flight per thread, so every line is read
+// once and whole; each thread owns rows i, i + 256, i + 512 and sums over j in
+// the same order as k_asm_local, so the two give identical results.
 constexpr int kAsmRowsPerThread = 3;
+constexpr int kAsmPieceBytes = 32768;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_asm_local_elem(DevMesh dm, const T *__restrict__ Sinv,
                                                         const double *__restrict__ r, double *__restrict__ zloc) {
-    const int e = blockIdx.x;
+    constexpr int kPiece = kAsmPieceBytes / (int)sizeof(T);  // entries per piece
+    constexpr int kVN = 16 / (int)sizeof(T);                 // entries per 16-byte load
+    constexpr int kLoads = kPiece / kVN / 256;                 // loads per thread and piece
+    typedef T vq __attribute__((ext_vector_type(kVN)));
+    const int e = blockIdx.x, tid = threadIdx.x;
     const int *to = dm.toff + 7 * e;
     const int f = to[6];
+    __shared__ __attribute__((aligned(16))) T sp[kPiece];
     __shared__ double sy[kAsmRowsPerThread * 256];
     for (int lf = 0; lf < 6; ++lf) {
         const int F = dm.elem_face[6 * e + lf];
         const int len = to[lf + 1] - to[lf];
-        for (int t = threadIdx.x; t < len; t += blockDim.x) sy[to[lf] + t] = r[dm.face_off[F] + t];
+        for (int t = tid; t < len; t += blockDim.x) sy[to[lf] + t] = r[dm.face_off[F] + t];
     }
-    __syncthreads();
     const T *M = Sinv + dm.asm_off[e];
-    int row[kAsmRowsPerThread];
-#pragma unroll
-    for (int q = 0; q < kAsmRowsPerThread; ++q) row[q] = min((int)threadIdx.x + 256 * q, f - 1);  // clamped reads
+    const int64_t n = (int64_t)f * f;
     double acc[kAsmRowsPerThread] = {};
-    int j = 0;
-    for (; j + 3 < f; j += 4) {
-        T a[4][kAsmRowsPerThread];
+    for (int64_t p0 = 0; p0 < n; p0 += kPiece) {
+        const int len = (int)min((int64_t)kPiece, n - p0);
+        const int units = (len + kVN - 1) / kVN;  // the last unit may take zeros of the padding
+        vq v[kLoads];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int q = 0; q < kLoads; ++q) {
+            const int u = tid + 256 * q;
+            if (u < units) v[q] = __builtin_nontemporal_load((const vq *)(M + p0) + u);
+        }
+        __syncthreads();  // the previous piece has been read (and, first, sy is complete)
 #pragma unroll
-            for (int q = 0; q < kAsmRowsPerThread; ++q) a[c][q] = M[(int64_t)(j + c) * f + row[q]];
+        for (int q = 0; q < kLoads; ++q) {
+            const int u = tid + 256 * q;
+            if (u < units) *(vq *)(sp + kVN * u) = v[q];
+        }
+        __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int q = 0; q < kAsmRowsPerThread; ++q) acc[q] += (double)a[c][q] * sy[j + c];
+        for (int q = 0; q < kAsmRowsPerThread; ++q) {
+            const int i = tid + 256 * q;
+            if (i >= f) continue;
+            // columns j with j f + i in [p0, p0 + len)
+            const int jlo = p0 > i ? (int)((p0 - i + f - 1) / f) : 0;
+            const int64_t last = p0 + len - 1 - i;
+            const int jhi = last >= 0 ? (int)(last / f) : -1;
+            const T *col = sp + ((int64_t)jlo * f + i - p0);
+            for (int j = jlo; j <= jhi; ++j, col += f) acc[q] += (double)*col * sy[j];
+        }
     }
-    for (; j < f; ++j)
-#pragma unroll
-        for (int q = 0; q < kAsmRowsPerThread; ++q) acc[q] += (double)M[(int64_t)j * f + row[q]] * sy[j];
     double *z = zloc + dm.tloc_off[e];
 #pragma unroll
     for (int q = 0; q < kAsmRowsPerThread; ++q)
-        if ((int)threadIdx.x + 256 * q < f) z[threadIdx.x + 256 * q] = acc[q];
+        if (tid + 256 * q < f) z[tid + 256 * q] = acc[q];
 }
 
 __global__ void __launch_bounds__(128) k_asm_gather(DevMesh dm, const double *__restrict__ zloc, double *__restrict__ z) {
