@@ -326,26 +326,40 @@ __global__ void __launch_bounds__(128) k_asm_gather(DevMesh dm, const double *__
 }
 
 // --------------------------------------------------------------------- GMRES
-constexpr int kDotBlocks = 256;
+constexpr int kDotBlocks = 1024;  // four per CU
+constexpr int kDotGroup = 8;      // vectors per pass over a block's slice of w
 
-// partial[b * stride + v] = sum over block b's slice of V[v] . w   (v < nv)
+// partial[b * stride + v] = sum over block b's slice of V[v] . w   (v < nv).
+// The vectors go kDotGroup at a time, so w is read once per group; each sum is
+// reduced within a wave by shuffles and across the four waves through LDS, in
+// a fixed order (deterministic).
 __global__ void __launch_bounds__(256) k_dot_partial(const double *__restrict__ V, int nv, int64_t ldv,
                                                      const double *__restrict__ w, int64_t N,
                                                      double *__restrict__ partial, int stride) {
-    __shared__ double red[256];
+    __shared__ double red[4][kDotGroup];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
     const int64_t i0 = blockIdx.x * chunk, i1 = min(N, i0 + chunk);
-    for (int v = 0; v < nv; ++v) {
-        const double *Vv = V + v * ldv;
-        double s = 0.0;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) s += Vv[i] * w[i];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
+    for (int v0 = 0; v0 < nv; v0 += kDotGroup) {
+        const int ng = min(kDotGroup, nv - v0);
+        double s[kDotGroup] = {};
+        for (int64_t i = i0 + tid; i < i1; i += blockDim.x) {
+            const double wi = w[i];
+#pragma unroll
+            for (int g = 0; g < kDotGroup; ++g)
+                if (g < ng) s[g] += V[(int64_t)(v0 + g) * ldv + i] * wi;
         }
-        if (threadIdx.x == 0) partial[blockIdx.x * stride + v] = red[0];
+#pragma unroll
+        for (int g = 0; g < kDotGroup; ++g) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s[g] += __shfl_down(s[g], off, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int g = 0; g < kDotGroup; ++g) red[wave][g] = s[g];
+        }
+        __syncthreads();
+        if (tid < ng) partial[(int64_t)blockIdx.x * stride + v0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
         __syncthreads();
     }
 }
