@@ -535,25 +535,60 @@ __global__ void __launch_bounds__(256) k_assemble_field_rows(DevMesh dm, Phys P,
                 sV[1][q][g3] = vd;
             }
             __syncthreads();
-            for (int t = tid; t < p1 * p1 * Np; t += blockDim.x) {
-                const int k = t % Np, q = t / Np;
-                const int i2 = q % p1, i3 = q / p1;
-                const int k1 = k % p1, k2 = (k / p1) % p1, k3 = k / (p1 * p1);
-                const int vq = (i2 * p1 + k1) * p1 + k2;
-                double v = 0.0;
-                for (int g3 = 0; g3 < nq; ++g3)
-                    v += (sL[i3][g3] * sV[0][vq][g3] + sD[i3][g3] * sV[1][vq][g3]) * sL[k3][g3];
-                if (faces) {
-                    // face terms of the faces that both node i and node k lie on (ascending lf)
+            if constexpr (p1 * p1 * p1 * p1 <= 256) {
+                // one pass of the workgroup: a thread takes the p1 outputs k = k12 + p1^2 k3
+                // that share the z-stage operands of (q, k1, k2), each summed over g3 in
+                // the same order as below (p <= 3)
+                for (int t = tid; t < p1 * p1 * p1 * p1; t += blockDim.x) {
+                    const int k12 = t % (p1 * p1), q = t / (p1 * p1);
+                    const int i2 = q % p1, i3 = q / p1;
+                    const int k1 = k12 % p1, k2 = k12 / p1;
+                    const int vq = (i2 * p1 + k1) * p1 + k2;
+                    double zl[nq];
+#pragma unroll
+                    for (int g3 = 0; g3 < nq; ++g3) zl[g3] = sL[i3][g3] * sV[0][vq][g3] + sD[i3][g3] * sV[1][vq][g3];
                     const int irow = i1 + p1 * (i2 + p1 * i3);
-                    unsigned m = sNm[irow] & sNm[k];
-                    while (m) {
-                        const int lf = __builtin_ctz(m);
-                        m &= m - 1;
-                        v += sF[lf * p1 * p1 * p1 * p1 + sNa[lf][irow] * p1 * p1 + sNa[lf][k]];
+                    double *dst = Er + (int64_t)(i1 + p1 * q) * ld + sblk * Np + k12;
+#pragma unroll
+                    for (int k3 = 0; k3 < p1; ++k3) {
+                        const int k = k12 + p1 * p1 * k3;
+                        double v = 0.0;
+#pragma unroll
+                        for (int g3 = 0; g3 < nq; ++g3) v += zl[g3] * sL[k3][g3];
+                        if (faces) {
+                            // face terms of the faces that both node i and node k lie on (ascending lf)
+                            unsigned m = sNm[irow] & sNm[k];
+                            while (m) {
+                                const int lf = __builtin_ctz(m);
+                                m &= m - 1;
+                                v += sF[lf * p1 * p1 * p1 * p1 + sNa[lf][irow] * p1 * p1 + sNa[lf][k]];
+                            }
+                        }
+                        __builtin_nontemporal_store(v, dst + p1 * p1 * k3);
                     }
                 }
-                __builtin_nontemporal_store(v, Er + (int64_t)(i1 + p1 * q) * ld + sblk * Np + k);
+            } else {
+                // one output per thread and pass (p = 4: 3125 outputs, 13 passes)
+                for (int t = tid; t < p1 * p1 * Np; t += blockDim.x) {
+                    const int k = t % Np, q = t / Np;
+                    const int i2 = q % p1, i3 = q / p1;
+                    const int k1 = k % p1, k2 = (k / p1) % p1, k3 = k / (p1 * p1);
+                    const int vq = (i2 * p1 + k1) * p1 + k2;
+                    double v = 0.0;
+                    for (int g3 = 0; g3 < nq; ++g3)
+                        v += (sL[i3][g3] * sV[0][vq][g3] + sD[i3][g3] * sV[1][vq][g3]) * sL[k3][g3];
+                    if (faces) {
+                        // face terms of the faces that both node i and node k lie on (ascending lf)
+                        const int irow = i1 + p1 * (i2 + p1 * i3);
+                        unsigned m = sNm[irow] & sNm[k];
+                        while (m) {
+                            const int lf = __builtin_ctz(m);
+                            m &= m - 1;
+                            v += sF[lf * p1 * p1 * p1 * p1 + sNa[lf][irow] * p1 * p1 + sNa[lf][k]];
+                        }
+                    }
+                    __builtin_nontemporal_store(v, Er + (int64_t)(i1 + p1 * q) * ld + sblk * Np + k);
+                }
             }
         }
     };
@@ -800,9 +835,10 @@ __global__ void __launch_bounds__(256) k_assemble_trace_rows(DevMesh dm, Phys P,
             for (int rr = 0; rr < nr; ++rr) {
                 double *dst = Et + (int64_t)(c * Nfp + a0 + rr) * ld;
                 const double *out = sOut[rr];
-                for (int col = tid; col < ld; col += blockDim.x) {
-                    const int idx = sMap[col];
-                    __builtin_nontemporal_store(idx >= 0 ? out[idx] : 0.0, dst + col);
+                for (int c2 = tid; c2 < ld / 2; c2 += blockDim.x) {  // ld and the row starts are multiples of 8
+                    const int i0 = sMap[2 * c2], i1 = sMap[2 * c2 + 1];
+                    const v2d v = {i0 >= 0 ? out[i0] : 0.0, i1 >= 0 ? out[i1] : 0.0};
+                    __builtin_nontemporal_store(v, (v2d *)(dst + 2 * c2));
                 }
             }
         }
