@@ -143,11 +143,13 @@ __global__ void __launch_bounds__(256) k_matvec(DevMesh dm, const double *__rest
 }
 
 // ------------------------------------------------------------- Schwarz setup
-// Systems [S_r' | I] (m rows, row-major, row stride e_ld(m, m)), m = f rounded up
-// to a multiple of 4; S_r' = [[S_r, 0], [0, I]] (decoupled padding unknowns).
-// One 32 x 32 tile of the system per workgroup: read with consecutive lanes on
-// consecutive rows (the BSR blocks are column-major), written through LDS with
-// consecutive lanes on consecutive columns (the system is row-major).
+// Systems [S_r' | I] (m rows, row-major, row stride e_ld(m, m) = 2m + 8), m = f
+// rounded up to a multiple of 4; S_r' = [[S_r, 0], [0, I]] (decoupled padding
+// unknowns).  k_asm_build writes the columns 0 .. m-1, one 32 x 32 tile per
+// workgroup: read with consecutive lanes on consecutive rows (the BSR blocks are
+// column-major), written through LDS with consecutive lanes on consecutive
+// columns (the system is row-major); k_asm_identity writes the columns
+// m .. 2m+7 (the identity, then zeros) with 16-byte nontemporal stores.
 template <typename T>
 __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__restrict__ S, T *__restrict__ sys) {
     const int e = blockIdx.z;
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__r
     const int f = to[6], m = asm_pad(f);
     const int ld = (int)e_ld(m, m);
     const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-    if (r0 >= m || c0 >= ld) return;  // uniform per block
+    if (r0 >= m || c0 >= m) return;  // uniform per block
     T *base = sys + dm.asmsys_off[e];
     __shared__ double tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -174,8 +176,6 @@ __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__r
             } else {
                 v = (r == c) ? 1.0 : 0.0;
             }
-        } else if (r < m && c < 2 * m) {
-            v = (c - m == r) ? 1.0 : 0.0;
         }
         tile[tx][ty + 8 * q] = v;
     }
@@ -183,7 +183,25 @@ __global__ void __launch_bounds__(256) k_asm_build(DevMesh dm, const double *__r
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int r = r0 + ty + 8 * q, c = c0 + tx;
-        if (r < m && c < ld) base[(int64_t)r * ld + c] = (T)tile[ty + 8 * q][tx];
+        if (r < m && c < m) base[(int64_t)r * ld + c] = (T)tile[ty + 8 * q][tx];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_asm_identity(DevMesh dm, T *__restrict__ sys) {
+    constexpr int kVN = 16 / (int)sizeof(T);
+    typedef T vq __attribute__((ext_vector_type(kVN)));
+    const int e = blockIdx.y;
+    const int f = dm.toff[7 * e + 6], m = asm_pad(f);
+    const int64_t ld = e_ld(m, m);
+    const int nv = (int)(ld - m) / kVN;  // 16-byte units of a row's right part (ld - m = m + 8)
+    T *base = sys + dm.asmsys_off[e] + m;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < (int64_t)m * nv; t += (int64_t)gridDim.x * 256) {
+        const int r = (int)(t / nv), u = (int)(t % nv);
+        vq v;
+#pragma unroll
+        for (int i = 0; i < kVN; ++i) v[i] = (kVN * u + i == r) ? T(1) : T(0);
+        __builtin_nontemporal_store(v, (vq *)(base + (int64_t)r * ld + kVN * u));
     }
 }
 
@@ -671,11 +689,27 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
         double acc[kRQ];
 #pragma unroll
         for (int q = 0; q < kRQ; ++q) acc[q] = 0.0;
-        for (int j = lane; j < f; j += 64) {
-            const double dj = sd[j];
+        // four column strides' loads in flight per lane; every acc[q] still adds its
+        // terms in increasing j
+        for (int j0 = lane; j0 < f; j0 += 4 * 64) {
+            double yv[4][kRQ];
 #pragma unroll
-            for (int q = 0; q < kRQ; ++q)
-                if (i + q < n) acc[q] += Y[(int64_t)(i + q) * ldy + j] * dj;
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < kRQ; ++q) {
+                    const int j = j0 + 64 * u;
+                    yv[u][q] = (j < f && i + q < n) ? Y[(int64_t)(i + q) * ldy + j] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + 64 * u;
+                if (j < f) {
+                    const double dj = sd[j];
+#pragma unroll
+                    for (int q = 0; q < kRQ; ++q)
+                        if (i + q < n) acc[q] += yv[u][q] * dj;
+                }
+            }
         }
 #pragma unroll
         for (int q = 0; q < kRQ; ++q) {
@@ -694,11 +728,25 @@ __global__ void __launch_bounds__(kRT) k_recover(DevMesh dm, int e0, int backsub
                 double acc[kRQ];
 #pragma unroll
                 for (int q = 0; q < kRQ; ++q) acc[q] = 0.0;
-                for (int c = i1 + lane; c < n; c += 64) {
-                    const double xc = sy[c];
+                for (int c0 = i1 + lane; c0 < n; c0 += 4 * 64) {
+                    double uv[4][kRQ];
 #pragma unroll
-                    for (int q = 0; q < kRQ; ++q)
-                        if (r + q < i1) acc[q] += E[(int64_t)(r + q) * ld + c] * xc;
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int q = 0; q < kRQ; ++q) {
+                            const int c = c0 + 64 * u;
+                            uv[u][q] = (c < n && r + q < i1) ? E[(int64_t)(r + q) * ld + c] : 0.0;
+                        }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int c = c0 + 64 * u;
+                        if (c < n) {
+                            const double xc = sy[c];
+#pragma unroll
+                            for (int q = 0; q < kRQ; ++q)
+                                if (r + q < i1) acc[q] += uv[u][q] * xc;
+                        }
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < kRQ; ++q) {
@@ -783,11 +831,15 @@ int launch_asm_setup(const hdg_ctx *ctx, int prec, const double *S, void *Sinv, 
     void *iwork = (void *)((char *)work + sys_bytes);
     // FP64 inverses for FP64 storage; FP32 storage is inverted in FP32 (FP32 matrix cores)
     const int mmax = asm_pad(ctx->max_f);
-    const dim3 bgrid((int)((e_ld(mmax, mmax) + 31) / 32), (mmax + 31) / 32, ctx->n_elem);
-    if (prec == HDG_FP64)
+    const dim3 bgrid((mmax + 31) / 32, (mmax + 31) / 32, ctx->n_elem);
+    const dim3 igrid(32, ctx->n_elem);
+    if (prec == HDG_FP64) {
         hipLaunchKernelGGL(k_asm_build<double>, bgrid, dim3(256), 0, s, dm, S, (double *)sys);
-    else
+        hipLaunchKernelGGL(k_asm_identity<double>, igrid, dim3(256), 0, s, dm, (double *)sys);
+    } else {
         hipLaunchKernelGGL(k_asm_build<float>, bgrid, dim3(256), 0, s, dm, S, (float *)sys);
+        hipLaunchKernelGGL(k_asm_identity<float>, igrid, dim3(256), 0, s, dm, (float *)sys);
+    }
     int err = run_asm_inversion(ctx, prec, sys, info, iwork, s);
     if (err) return err;
     const int maxf = ctx->max_f;
