@@ -76,4 +76,24 @@ def test_entry_points_reject_null_context():
     assert L.hdg_asm_block_apply(None, 0, None, None, None, None, 0, None) == -1
     assert L.hdg_local_residual_jacobian(None, 0, 1, *([None] * 8), 0, None) == -1
     assert L.hdg_bsr_pattern(None, None, None, None) == -1
+
+
+def test_peak_probes_reject_bad_arguments_on_the_host():
+    import ctypes
+    L = hdg.load_library()
+    p = ctypes.c_void_p(4096)  # never dereferenced: every call below is rejected before any launch
+    q = ctypes.c_void_p(4096 + 65536)
+    assert L.hdg_peak_mfma(16, 1, 1, 1.0, p, None) == -1
+    assert L.hdg_peak_mfma(64, 0, 1, 1.0, p, None) == -1
+    assert L.hdg_peak_mfma(32, (1 << 20) + 1, 1, 1.0, p, None) == -1
+    assert L.hdg_peak_mfma(64, 1, 0, 1.0, p, None) == -1
+    assert L.hdg_peak_mfma(64, 1, 1, 1.0, None, None) == -1
+    assert L.hdg_peak_read(p, 0, q, None) == -1
+    assert L.hdg_peak_read(p, 24, q, None) == -1
+    assert L.hdg_peak_read(ctypes.c_void_p(4104), 32, q, None) == -1
+    assert L.hdg_peak_read(p, 32, None, None) == -1
+    assert L.hdg_peak_copy(p, q, 0, None) == -1
+    assert L.hdg_peak_copy(p, q, 40, None) == -1
+    assert L.hdg_peak_copy(p, ctypes.c_void_p(4096 + 1024), 2048, None) == -1  # overlapping
+    assert L.hdg_peak_copy(None, q, 16, None) == -1
     assert L.hdg_status_string(-5) == b"workspace too small"
